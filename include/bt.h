@@ -1,0 +1,173 @@
+/*
+ * bt.h - C ABI of the MI355X bitruss library (libbt.so).
+ *
+ * Bitruss decomposition of a bipartite graph with the BE-Index of
+ * Wang, Lin, Qin, Zhang, Zhang, "Efficient Bitruss Decomposition for
+ * Large-scale Bipartite Graphs" (ICDE 2020):
+ *   - butterfly support of every edge (Section II, Definition 2 and the
+ *     counting step of Algorithm 4),
+ *   - the BE-Index: maximal priority-obeyed blooms, their edge links and
+ *     twin edges (Section IV, Definitions 6-8, Algorithm 3),
+ *   - bitruss numbers (Section II, Definitions 4-5) by peeling through
+ *     blooms with batch edge and batch bloom processing (Section V-B,
+ *     Algorithm 5).
+ *
+ * Conventions shared by every entry point
+ *   Graph: upper-major CSR, all pointers DEVICE pointers.
+ *     row_ptr int64[n_upper+1]: row_ptr[0] = 0, non-decreasing,
+ *                               row_ptr[n_upper] = m.
+ *     col     int32[m]: lower ids in [0, n_lower), strictly increasing
+ *                       within a row (the edge set is a set: Section II).
+ *   Edge identity: edge e is CSR position e; every per-edge output is
+ *     indexed by it.  Vertex priority (Definition 6) orders by degree, ties
+ *     by id, with every upper id above every lower id (Section II): lower
+ *     vertex j has id j, upper vertex i has id n_lower + i.
+ *   Limits: n_upper + n_lower < 2^31 and m < 2^31 (else BT_EOVERFLOW).
+ *     A support is then at most m - 1 (Lemma 8's argument), so it fits
+ *     32 bits internally; outputs are int64.  The number of
+ *     priority-obeyed wedges must be below 2^32 (else BT_EOVERFLOW).
+ *   Streams: every call enqueues its work on `stream` (0 = the null
+ *     stream) and returns after the results are complete on that stream;
+ *     host-side outputs are written before return.
+ *   Ownership: the caller owns the graph and every output buffer.  The
+ *     library owns its scratch memory (a device workspace cached between
+ *     calls, released by bt_release_workspace) and the bt_index handles
+ *     until bt_index_free.
+ *   Errors: a non-zero bt_status leaves outputs unspecified;
+ *     bt_last_error() returns a thread-local message for the last failure.
+ *   Threading: calls that use the shared workspace (bt_support,
+ *     bt_index_build, bt_decompose, bt_decompose_batch) serialise on an
+ *     internal lock.
+ */
+#ifndef BT_H
+#define BT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bt_status {
+    BT_OK = 0,
+    BT_EINVAL = 1,     /* malformed graph or argument; no output written */
+    BT_ENOMEM = 2,     /* device allocation failed; bt_last_error names the size */
+    BT_EOVERFLOW = 3,  /* a size limit above was exceeded */
+    BT_EDEVICE = 4,    /* a HIP call failed */
+    BT_EBUSY = 5       /* engine cannot admit the request now */
+} bt_status;
+
+typedef struct bt_csr {
+    int32_t n_upper;
+    int32_t n_lower;
+    int64_t m;
+    const int64_t *row_ptr; /* device, int64[n_upper + 1] */
+    const int32_t *col;     /* device, int32[m] */
+} bt_csr;
+
+/* Counters of one decomposition (all filled by bt_decompose when non-NULL). */
+typedef struct bt_stats {
+    int64_t butterflies;      /* total butterflies of the graph */
+    int64_t wedges_po;        /* priority-obeyed wedges walked (Definition 9) */
+    int64_t blooms;           /* maximal priority-obeyed blooms */
+    int64_t bloom_wedges;     /* sum of bloom numbers = wedges stored in the index */
+    int64_t index_bytes;      /* device bytes of the BE-Index */
+    int64_t levels;           /* distinct bitruss levels visited by the peel */
+    int64_t rounds;           /* peel rounds (frontiers processed) */
+    int64_t max_phi;          /* largest bitruss number */
+    int64_t support_updates;  /* support decrements issued by the peel */
+    int64_t bloom_visits;     /* touched-bloom visits in batch bloom processing */
+    float ms_prepare;         /* validation, priority order, rank-space CSR */
+    float ms_count;           /* wedge counting and index emission */
+    float ms_link;            /* edge-to-wedge links */
+    float ms_peel;            /* peel */
+} bt_stats;
+
+/* Opaque device-resident BE-Index. */
+typedef struct bt_index bt_index;
+
+typedef struct bt_index_info {
+    int64_t m;
+    int64_t blooms;        /* n_B */
+    int64_t bloom_wedges;  /* n_W: each wedge is a twin-edge pair */
+    int64_t links;         /* 2 n_W edge-to-bloom links */
+    int64_t butterflies;
+    int64_t wedges_po;
+    int64_t bytes;         /* device memory held by the index */
+} bt_index_info;
+
+/*
+ * Butterfly support of every edge (Definition 2; the counting step of
+ * Algorithm 4, done through priority-obeyed wedges as in Algorithm 3's
+ * first sweep, with Lemmas 1-3 turning bloom sizes into supports).
+ *   g               graph (device CSR), validated on the device.
+ *   sup_out         device int64[m]: support of edge e (may be NULL if m == 0).
+ *   butterflies_out host int64 (nullable): total butterflies.
+ */
+bt_status bt_support(const bt_csr *g, int64_t *sup_out, int64_t *butterflies_out,
+                     hipStream_t stream);
+
+/*
+ * Build the BE-Index (Section IV, Algorithm 3): every maximal
+ * priority-obeyed bloom with its bloom number, its wedges (twin-edge
+ * pairs, Definition 8) and, per edge, the links to the blooms holding it.
+ *   out  receives a handle owning device memory; free with bt_index_free.
+ */
+bt_status bt_index_build(const bt_csr *g, bt_index **out, hipStream_t stream);
+
+bt_status bt_index_info_get(const bt_index *idx, bt_index_info *info);
+
+/*
+ * Copy the index to HOST arrays (for inspection and tests).  Bloom b owns
+ * wedges [bloom_woff[b], bloom_woff[b+1]); its bloom number is that length.
+ * Wedge w is the twin pair (wedge_ea[w], wedge_eb[w]): wedge_ea is the edge
+ * at the bloom's highest-priority vertex, wedge_eb the edge at the other
+ * dominant-layer vertex.  edge_link_off/edge_link (nullable) give, for
+ * edge e, the wedges holding it: edge_link[edge_link_off[e] ..
+ * edge_link_off[e+1]).  Sizes: bloom_woff[blooms+1], wedge_*[bloom_wedges],
+ * edge_link_off[m+1], edge_link[2*bloom_wedges], sup[m] (nullable).
+ */
+bt_status bt_index_export(const bt_index *idx, int64_t *bloom_woff, int32_t *wedge_ea,
+                          int32_t *wedge_eb, int64_t *edge_link_off, int64_t *edge_link,
+                          int64_t *sup);
+
+void bt_index_free(bt_index *idx);
+
+/*
+ * Bitruss number of every edge (Definition 5): support counting, index
+ * construction and the bulk-synchronous peel through blooms with batch
+ * edge and batch bloom processing (Algorithm 5).
+ *   sup_out  device int64[m] (nullable): initial supports.
+ *   phi_out  device int64[m]: bitruss numbers.
+ *   stats    host (nullable): counters and per-phase device times.
+ */
+bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
+                       bt_stats *stats, hipStream_t stream);
+
+/*
+ * Decompose many independent graphs in shared launches.  gs is a HOST
+ * array of n_graphs descriptors (device CSRs); sup_out / phi_out are HOST
+ * arrays of n_graphs device pointers (sup_out may be NULL, or hold NULLs).
+ * Results equal bt_decompose on each graph.  stats (nullable) receives the
+ * sums over all graphs (levels and rounds: the maximum).
+ */
+bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const *sup_out,
+                             int64_t *const *phi_out, bt_stats *stats, hipStream_t stream);
+
+/* Free the cached device workspace (it regrows on the next call). */
+void bt_release_workspace(void);
+
+/* Thread-local text of the last error. */
+const char *bt_last_error(void);
+
+/* Library version string. */
+const char *bt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BT_H */

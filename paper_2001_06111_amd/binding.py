@@ -1,0 +1,216 @@
+"""Python binding of libbt.so: argument marshalling only.
+
+Each function has the name of the C entry point it calls and takes torch
+tensors that already live on the GPU (PyTorch is used for device memory and
+streams; all compute runs in the library's HIP kernels).  The binding fails
+loudly when the library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbt.so")
+
+BT_OK, BT_EINVAL, BT_ENOMEM, BT_EOVERFLOW, BT_EDEVICE, BT_EBUSY = range(6)
+_NAMES = {1: "BT_EINVAL", 2: "BT_ENOMEM", 3: "BT_EOVERFLOW", 4: "BT_EDEVICE", 5: "BT_EBUSY"}
+
+
+class BtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class bt_csr(ctypes.Structure):
+    _fields_ = [("n_upper", ctypes.c_int32), ("n_lower", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class bt_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "butterflies", "wedges_po", "blooms", "bloom_wedges", "index_bytes", "levels",
+        "rounds", "max_phi", "support_updates", "bloom_visits")] + [
+        (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class bt_index_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "m", "blooms", "bloom_wedges", "links", "butterflies", "wedges_po", "bytes")]
+
+
+EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
+            "bt_index_free", "bt_decompose", "bt_decompose_batch", "bt_release_workspace",
+            "bt_last_error", "bt_version"]
+
+_lib = None
+
+
+def load():
+    """Open libbt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.bt_support.argtypes = [ctypes.POINTER(bt_csr), p, ctypes.POINTER(i64), p]
+        L.bt_index_build.argtypes = [ctypes.POINTER(bt_csr), ctypes.POINTER(p), p]
+        L.bt_index_info_get.argtypes = [p, ctypes.POINTER(bt_index_info)]
+        L.bt_index_export.argtypes = [p, p, p, p, p, p, p]
+        L.bt_index_free.argtypes = [p]
+        L.bt_index_free.restype = None
+        L.bt_decompose.argtypes = [ctypes.POINTER(bt_csr), p, p, ctypes.POINTER(bt_stats), p]
+        L.bt_decompose_batch.argtypes = [ctypes.POINTER(bt_csr), i32, ctypes.POINTER(p),
+                                         ctypes.POINTER(p), ctypes.POINTER(bt_stats), p]
+        L.bt_release_workspace.restype = None
+        L.bt_last_error.restype = ctypes.c_char_p
+        L.bt_version.restype = ctypes.c_char_p
+        for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
+                     "bt_decompose", "bt_decompose_batch"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != BT_OK:
+        raise BtError(rc, load().bt_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+class DeviceGraph:
+    """A graph in device memory: upper-major CSR as torch tensors."""
+
+    def __init__(self, n_upper: int, n_lower: int, row_ptr: torch.Tensor, col: torch.Tensor):
+        assert row_ptr.dtype == torch.int64 and col.dtype == torch.int32
+        assert row_ptr.is_cuda and col.is_cuda
+        self.n_upper, self.n_lower = int(n_upper), int(n_lower)
+        self.row_ptr, self.col = row_ptr.contiguous(), col.contiguous()
+
+    @property
+    def m(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def upload(cls, g, device="cuda"):
+        """From any object with n_upper, n_lower, row_ptr, col (numpy)."""
+        rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int64)).to(device)
+        c = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).to(device)
+        return cls(g.n_upper, g.n_lower, rp, c)
+
+    def csr(self) -> bt_csr:
+        return bt_csr(self.n_upper, self.n_lower, self.m, self.row_ptr.data_ptr(),
+                      self.col.data_ptr() if self.m > 0 else 0)
+
+
+def bt_support(g: DeviceGraph, stream=None):
+    """(int64 supports on the device, total butterflies)."""
+    L = load()
+    sup = torch.empty(g.m, dtype=torch.int64, device=g.col.device)
+    bf = ctypes.c_int64(0)
+    c = g.csr()
+    _check(L.bt_support(ctypes.byref(c), _ptr(sup), ctypes.byref(bf), _stream(stream)))
+    return sup, int(bf.value)
+
+
+def bt_decompose(g: DeviceGraph, want_sup: bool = True, stats: bool = False, stream=None,
+                 out_phi: torch.Tensor | None = None, out_sup: torch.Tensor | None = None):
+    """(supports or None, bitruss numbers, stats dict or None)."""
+    L = load()
+    dev = g.col.device
+    phi = out_phi if out_phi is not None else torch.empty(g.m, dtype=torch.int64, device=dev)
+    sup = out_sup if out_sup is not None else (
+        torch.empty(g.m, dtype=torch.int64, device=dev) if want_sup else None)
+    st = bt_stats()
+    c = g.csr()
+    _check(L.bt_decompose(ctypes.byref(c), _ptr(sup), _ptr(phi),
+                          ctypes.byref(st) if stats else None, _stream(stream)))
+    return sup, phi, (st.as_dict() if stats else None)
+
+
+def bt_decompose_batch(graphs, want_sup: bool = True, stats: bool = False, stream=None):
+    """Lists of supports and bitruss numbers (device tensors), plus summed stats."""
+    L = load()
+    n = len(graphs)
+    dev = graphs[0].col.device if n else "cuda"
+    phis = [torch.empty(g.m, dtype=torch.int64, device=dev) for g in graphs]
+    sups = [torch.empty(g.m, dtype=torch.int64, device=dev) for g in graphs] if want_sup else None
+    arr = (bt_csr * max(n, 1))(*[g.csr() for g in graphs])
+    pp = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value or 0 for t in phis])
+    sp = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value or 0 for t in sups]) if want_sup else None
+    st = bt_stats()
+    _check(L.bt_decompose_batch(arr, n, sp, pp, ctypes.byref(st) if stats else None,
+                                _stream(stream)))
+    return sups, phis, (st.as_dict() if stats else None)
+
+
+class BtIndex:
+    """Handle of a device-resident BE-Index (bt_index_build / bt_index_free)."""
+
+    def __init__(self, handle, m: int):
+        self._h = handle
+        self.m = m
+
+    def info(self) -> dict:
+        info = bt_index_info()
+        _check(load().bt_index_info_get(self._h, ctypes.byref(info)))
+        return {n: getattr(info, n) for n, _ in info._fields_}
+
+    def export(self) -> dict:
+        """Host copies: bloom_woff, wedge_ea, wedge_eb, link_off, link, sup (numpy)."""
+        inf = self.info()
+        nb, nw = inf["blooms"], inf["bloom_wedges"]
+        out = dict(bloom_woff=np.zeros(nb + 1, np.int64), wedge_ea=np.zeros(nw, np.int32),
+                   wedge_eb=np.zeros(nw, np.int32), link_off=np.zeros(self.m + 1, np.int64),
+                   link=np.zeros(2 * nw, np.int64), sup=np.zeros(self.m, np.int64))
+
+        def p(a):
+            return a.ctypes.data_as(ctypes.c_void_p)
+        _check(load().bt_index_export(self._h, p(out["bloom_woff"]), p(out["wedge_ea"]),
+                                      p(out["wedge_eb"]), p(out["link_off"]), p(out["link"]),
+                                      p(out["sup"])))
+        return out
+
+    def free(self):
+        if self._h:
+            load().bt_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def bt_index_build(g: DeviceGraph, stream=None) -> BtIndex:
+    L = load()
+    h = ctypes.c_void_p(0)
+    c = g.csr()
+    _check(L.bt_index_build(ctypes.byref(c), ctypes.byref(h), _stream(stream)))
+    return BtIndex(h, g.m)
+
+
+def bt_release_workspace():
+    load().bt_release_workspace()
+
+
+def bt_version() -> str:
+    return load().bt_version().decode()

@@ -1,0 +1,165 @@
+// common.h - shared host/device helpers of the bitruss library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bt.h"
+
+namespace bt {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+
+struct Error {
+    bt_status status;
+    std::string msg;
+};
+
+#define BT_HIP(call)                                                           \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            throw ::bt::Error{BT_EDEVICE, std::string(#call) + ": " +          \
+                                              hipGetErrorString(e_)};          \
+    } while (0)
+
+#define BT_CHECK_LAUNCH() BT_HIP(hipGetLastError())
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int bits_for(uint64_t v) {  // bits needed to store values in [0, v]
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+// ---------------------------------------------------------- device memory
+
+// A named set of device buffers that grow on demand and are kept between
+// calls.  Buffers are 256-byte aligned.  Not thread-safe: owners lock.
+class Workspace {
+public:
+    ~Workspace();
+    void *get(const char *name, size_t bytes);
+    template <typename T> T *get(const char *name, int64_t count) {
+        return static_cast<T *>(get(name, (size_t)(count > 0 ? count : 1) * sizeof(T)));
+    }
+    void release();
+    size_t bytes() const;
+
+private:
+    struct Buf {
+        std::string name;
+        void *ptr = nullptr;
+        size_t cap = 0;
+    };
+    std::vector<Buf> bufs_;
+};
+
+void *device_alloc(size_t bytes);  // throws BT_ENOMEM with the size
+void device_free(void *p);
+
+// Pinned host scratch for small device-to-host reads (grows, kept).
+int64_t *host_scalars(int n);
+
+// ------------------------------------------------------ wave primitives
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (uint64_t(1) << lane_id()) - 1;
+}
+
+template <typename T> __device__ __forceinline__ T wave_inclusive_sum(T v) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T t = __shfl_up(v, d, kWave);
+        if (lane_id() >= d) v += t;
+    }
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_or(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v |= __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        T o = __shfl_xor(v, d, kWave);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Block-wide exclusive sum; `scratch` holds one T per wave.  Returns the
+// thread's exclusive prefix and writes the block total to *total.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T *scratch, T *total) {
+    const int nw = blockDim.x / kWave;
+    const int w = threadIdx.x / kWave;
+    T inc = wave_inclusive_sum(v);
+    if (lane_id() == kWave - 1) scratch[w] = inc;
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        T s = threadIdx.x < nw ? scratch[threadIdx.x] : T(0);
+        T si = wave_inclusive_sum(s);
+        if (threadIdx.x < nw) scratch[threadIdx.x] = si - s;
+        if (threadIdx.x == nw - 1) scratch[nw] = si;
+    }
+    __syncthreads();
+    T r = scratch[w] + inc - v;
+    *total = scratch[nw];
+    __syncthreads();
+    return r;
+}
+
+// Push `pred`-selected values to a global list with one atomic per wave.
+template <typename T>
+__device__ __forceinline__ void wave_push(bool pred, T val, T *list, int32_t *count) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, (int)__popcll(mask));
+    base = __shfl(base, leader, kWave);
+    if (pred) list[base + __popcll(mask & lanemask_lt())] = val;
+}
+
+// ------------------------------------------------- host-side primitives
+// (prims.hip) All enqueue on `s`; sizes are host values.
+
+// out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
+void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, Workspace &ws,
+                        hipStream_t s);
+void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, Workspace &ws,
+                               hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `key_bits` bits.
+// Sorted data ends in keys/vals (buffers are ping-ponged with ws scratch).
+void radix_sort_u64_u32(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits,
+                        Workspace &ws, hipStream_t s);
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+int grid_for(int64_t n, int block, int max_blocks = 1 << 20);
+
+}  // namespace bt

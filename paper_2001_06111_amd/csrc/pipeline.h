@@ -1,0 +1,91 @@
+// pipeline.h - stages of the hot path and the device views they share.
+#pragma once
+
+#include "common.h"
+
+namespace bt {
+
+// Rank-space adjacency (built by prepare()).
+//
+// Vertices are renumbered so that each layer occupies a contiguous range in
+// increasing priority (Definition 6: degree, ties by id, upper ids above
+// lower ids): lower layer [0, n_lower), upper layer [n_lower, n).  Row x
+// lists x's neighbours (new ids) in increasing priority with the edge id of
+// each entry.  low[x] counts the neighbours of lower priority than x, so
+// they form the row's prefix.  For a prefix entry (x -> y), rev is the
+// position of x in row y, which is the number of y's neighbours of lower
+// priority than x: the wedges (x, y, z) with p(y), p(z) < p(x) are
+// exactly z = adj[off[y] + t] for t < rev.
+struct RankCSR {
+    int32_t n_lower = 0, n = 0;
+    int64_t m = 0;
+    int64_t *off = nullptr;   // [n + 1]
+    int32_t *adj = nullptr;   // [2m] neighbour new id
+    int32_t *eid = nullptr;   // [2m] edge id
+    int32_t *rev = nullptr;   // [2m] z-prefix length for prefix entries, else 0
+    int32_t *low = nullptr;   // [n]
+    int64_t *wpre = nullptr;  // [2m + 1] exclusive prefix of rev: wedge work
+    int64_t wedges_po = 0;    // priority-obeyed wedges (host copy)
+    int32_t max_deg = 0;
+};
+
+// Work items of the wedge sweeps.
+struct WedgeTask {
+    int32_t x;     // start vertex (new id)
+    int32_t zlo;   // dense mode: counter range [zlo, zhi); hash mode: unused
+    int32_t zhi;
+    int32_t cap;   // hash mode: table slots (power of two); dense: zhi - zlo
+};
+
+struct TaskLists {
+    WedgeTask *hash = nullptr;
+    WedgeTask *dense = nullptr;
+    int64_t n_hash = 0, n_dense = 0;
+};
+
+// BE-Index arrays (device).  Blooms own contiguous wedge ranges
+// [bwoff[b], bwoff[b+1]); a wedge is a twin pair of edges.
+struct IndexArrays {
+    int64_t n_b = 0, n_w = 0;   // host copies after build
+    int64_t cap_b = 0, cap_w = 0;
+    uint32_t *bwoff = nullptr;  // [cap_b + 1]
+    int32_t *bk = nullptr;      // [cap_b] bloom number (live wedges)
+    int32_t *wea = nullptr;     // [cap_w] edge at the highest-priority vertex
+    int32_t *web = nullptr;     // [cap_w] twin edge
+    int32_t *wbl = nullptr;     // [cap_w] bloom of the wedge
+    uint64_t *supl = nullptr;   // [m] (links << 32) | support while building
+    int64_t *link_off = nullptr;  // [m + 1]
+    uint32_t *link = nullptr;     // [2 cap_w]
+    uint64_t *cursor = nullptr;   // device (blooms << 32) | wedges allocated
+    int64_t *butterflies = nullptr;  // device scalar
+};
+
+// Validates the CSR and builds the rank-space adjacency in `ws`.
+// Throws Error{BT_EINVAL} for malformed input.
+void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s);
+
+// Splits start vertices into wedge tasks (sync point: reads counts).
+void make_tasks(const RankCSR &r, TaskLists &t, Workspace &ws, hipStream_t s);
+
+// Support only: sup_out[e] (int64, may be null) and the butterfly total
+// (device scalar *bf, must be zeroed by the caller).
+void count_support(const RankCSR &r, const TaskLists &t, uint64_t *supl, int64_t *bf,
+                   hipStream_t s);
+
+// Counting plus index emission into `ix` (arrays sized by the caller from
+// r.wedges_po).  Fills supl and cursor; then builds the link lists.
+void build_index(const RankCSR &r, const TaskLists &t, IndexArrays &ix, Workspace &ws,
+                 hipStream_t s);
+
+// Peel through the index.  sup_out (int64, nullable) receives the initial
+// supports, phi_out (int64) the bitruss numbers.
+struct PeelCounters {
+    int64_t levels = 0, rounds = 0, max_phi = 0, updates = 0, bloom_visits = 0;
+};
+void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
+          PeelCounters &pc, Workspace &ws, hipStream_t s);
+
+// supl low halves to int64 supports.
+void supl_to_sup(const uint64_t *supl, int64_t *sup, int64_t m, hipStream_t s);
+
+}  // namespace bt

@@ -1,0 +1,130 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Supports, butterfly totals and bitruss numbers are integers and must match
+bit for bit; the index must equal the definition-level one after canonical
+ordering.
+"""
+import json
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2001_06111_amd import binding, synth
+from tests import graphs
+from tests.gpu_util import canonical_gpu_index, check_index, gpu_decompose, oracle_all, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _parity(g, stats=True):
+    sup, phi, st = gpu_decompose(g, stats=stats)
+    osup, obf, ophi = oracle_all(g)
+    assert np.array_equal(sup, osup), f"{g.name}: support mismatch"
+    assert np.array_equal(phi, ophi), f"{g.name}: bitruss mismatch"
+    if stats:
+        assert st["butterflies"] == obf
+    return st
+
+
+def test_worked_example_gpu():
+    for grey in (True, False):
+        g, nm, fx = graphs.worked_example(grey)
+        st = _parity(g)
+        sup, phi, _ = gpu_decompose(g)
+        for name, val in fx["support"].items():
+            assert sup[nm[name]] == val
+        for i in range(9):
+            assert phi[nm[f"e{i}"]] == fx["phi"][f"e{i}"]
+        idx = binding.bt_index_build(upload(g))
+        check_index(g, idx.export())
+        idx.free()
+
+
+def test_support_entry_point():
+    g = synth.uniform(200, 300, 3000, 9)
+    s, bf = binding.bt_support(upload(g))
+    osup, obf, _ = oracle.support(g.n_upper, g.n_lower, g.row_ptr, g.col)
+    assert np.array_equal(s.cpu().numpy(), osup) and bf == obf
+
+
+def test_special_graphs_gpu():
+    for g in [graphs.fig2a(), graphs.k2_1001(), synth.complete(7, 9), synth.complete(1, 5),
+              graphs.cycle(2), graphs.cycle(6), graphs.star(50), graphs.random_forest(40, 30, 1)]:
+        _parity(g)
+    g = graphs.k2_1001()
+    idx = binding.bt_index_build(upload(g))
+    inf = idx.info()
+    assert inf["blooms"] == 1 and inf["bloom_wedges"] == 1001
+    check_index(g, idx.export())
+
+
+def test_empty_and_edgeless():
+    g = synth.from_edges(3, 4, [])
+    sup, phi, st = gpu_decompose(g, stats=True)
+    assert sup.size == 0 and phi.size == 0 and st["butterflies"] == 0
+    g = synth.from_edges(0, 0, [])
+    sup, phi, st = gpu_decompose(g, stats=True)
+    assert sup.size == 0
+
+
+def test_exhaustive_3x3_gpu():
+    for g in graphs.all_graphs(3, 3):
+        sup, phi, _ = gpu_decompose(g)
+        osup, _, ophi = oracle_all(g)
+        assert np.array_equal(sup, osup) and np.array_equal(phi, ophi)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_dense_gpu(seed):
+    rng = np.random.default_rng(100 + seed)
+    g = graphs.random_dense(int(rng.integers(5, 40)), int(rng.integers(5, 40)),
+                            float(rng.uniform(0.2, 0.9)), seed)
+    _parity(g)
+    idx = binding.bt_index_build(upload(g))
+    check_index(g, idx.export())
+
+
+def test_uniform_10k_gpu():
+    """The small plain workload: full parity, index equal to the definition."""
+    g = synth.plain_uniform_10k()
+    _parity(g)
+    idx = binding.bt_index_build(upload(g))
+    check_index(g, idx.export())
+
+
+@pytest.mark.parametrize("m", [20_000, 200_000])
+def test_scaled_chunglu_gpu(m):
+    _parity(synth.scaled_chunglu(m, seed=3))
+
+
+def test_invalid_input_rejected():
+    g = synth.uniform(10, 10, 30, 1)
+    bad_col = g.col.copy()
+    bad_col[3] = 99
+    bad_sorted = g.col.copy()
+    r = int(np.argmax(np.diff(g.row_ptr) >= 2))
+    a = int(g.row_ptr[r])
+    bad_sorted[a], bad_sorted[a + 1] = bad_sorted[a + 1], bad_sorted[a]
+    bad_rp = g.row_ptr.copy()
+    bad_rp[-1] = g.m + 5
+    for rp, c in [(g.row_ptr, bad_col), (g.row_ptr, bad_sorted), (bad_rp, g.col)]:
+        dg = binding.DeviceGraph(g.n_upper, g.n_lower, torch.from_numpy(rp).cuda(),
+                                 torch.from_numpy(c).cuda())
+        with pytest.raises(binding.BtError) as ei:
+            binding.bt_decompose(dg)
+        assert ei.value.status == binding.BT_EINVAL
+    # the library still works afterwards
+    _parity(g)
+
+
+def test_batch_equals_plain():
+    gs = [synth.batch_graph(i) for i in range(12)]
+    dgs = [upload(g) for g in gs]
+    sups, phis, st = binding.bt_decompose_batch(dgs, stats=True)
+    torch.cuda.synchronize()
+    for g, s, p in zip(gs, sups, phis):
+        osup, _, ophi = oracle_all(g)
+        assert np.array_equal(s.cpu().numpy(), osup) and np.array_equal(p.cpu().numpy(), ophi)
