@@ -1,24 +1,46 @@
 // peel.hip - bulk-synchronous peel through blooms (Algorithm 5: batch edge
-// and batch bloom processing).
+// and batch bloom processing), driven entirely on the device.
 //
 // State: sup (int32, unclamped), phi (int32, -1 while the edge remains),
 // one alive bit per wedge, per bloom its live wedge count k and the count C
 // of wedges removed this round.  A round with level L and frontier F (the
 // remaining edges with support <= L):
-//   A. every edge of F gets phi = L; for each of its wedges still alive the
-//      wedge is killed (one winner per wedge), C[B] += 1 for its bloom B and
-//      the twin edge loses all of its k[B] - 1 butterflies in B;
+//   A. every edge of F gets phi = L; each of its wedges still alive is
+//      killed (one winner per wedge), C[B] += 1 for its bloom B, and the
+//      twin edge loses all of its k[B] - 1 butterflies in B;
 //   B. in every bloom touched in A, each surviving wedge's two edges lose
-//      C[B] butterflies (the bloom shrinks from k to k - C), then
-//      k[B] -= C[B], C[B] = 0; once k[B] <= 1 the bloom holds no butterfly
-//      and its last wedge is retired.
+//      C[B] butterflies (the bloom shrinks from k to k - C); then
+//      k[B] -= C[B], C[B] = 0.  Once k[B] <= 1 the bloom holds no
+//      butterfly and its last wedge is retired.
 // The paper clamps decremented supports at the round's minimum (max(MBS,
 // .)); subtracting unclamped and treating every support <= L as "at level
 // L" gives the same bitruss numbers, since max(M, max(M, a - d1) - d2) =
-// max(M, a - d1 - d2).  A decrement that takes a support from above L to
-// at most L puts the edge in the next frontier; when a frontier is empty
-// the level rises to the minimum remaining support.
+// max(M, a - d1 - d2).  A decrement that takes a support from above L to at
+// most L puts the edge in the next frontier.  When a frontier is empty the
+// level rises to the minimum remaining support.
+//
+// Device-driven rounds.  A round is two kernels that read their sizes from
+// a control block, so rounds are replayed from a captured HIP graph with
+// no host round trip:
+//   k_phase_a  normal round: the frontier edges' links, 64 per work item;
+//              gather round (first round of a level): the frontier becomes
+//              the active edges with support <= level, and the active set
+//              is compacted;
+//   k_phase_b  touched blooms, 64 wedges per work item; the last block to
+//              finish picks the next round: normal while a frontier exists,
+//              else a gather round at level + 1 (or, when a gather finds
+//              nothing, at the smallest support it saw).
+// One element per lane keeps every wave's chain of dependent atomics short.
+// The active set holds the remaining edges with support below a threshold T
+// (a decrement that crosses T appends the edge).  When no active edge
+// remains the device raises `stall` and the host rebuilds the set with a
+// larger T from a histogram of the remaining supports.  Lists that one
+// round fills and the next consumes are double-buffered by round parity;
+// every counter is reset by a kernel that does not read it.
 #include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
 
 #include "pipeline.h"
 
@@ -27,140 +49,353 @@ namespace bt {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kLinkChunk = kWave;   // links per phase-A work item (one per lane)
+constexpr int kWedgeChunk = kWave;  // wedges per phase-B work item (one per lane)
+constexpr int kGridA = 2048;
+constexpr int kGridB = 2048;
 
-struct PeelCtl {
-    int32_t n_front;
-    int32_t n_next;
-    int32_t n_touched;
-    int32_t level;
-    int32_t min_sup;
-    int32_t pad;
-    unsigned long long updates;
-    unsigned long long bloom_visits;
+typedef unsigned long long u64;
+
+enum : int32_t { kNormal = 0, kGather = 1 };
+
+// A counter alone on its cache line (contended atomics do not share lines).
+struct alignas(128) Counter {
+    u64 v;
 };
 
-__device__ __forceinline__ void dec_support(int32_t *sup, int32_t e, int32_t d, int32_t level,
-                                            bool active, int32_t *next, int32_t *n_next) {
-    bool push = false;
-    if (active) {
-        const int32_t old = atomicSub(&sup[e], d);
-        push = old > level && old - d <= level;
-    }
-    wave_push(push, e, next, n_next);
+struct PeelCtl {
+    Counter nf[2];      // frontier work items by round parity
+    Counter ntc[2];     // bloom work items by round parity
+    Counter na[2];      // active-set entries by buffer
+    Counter remaining;  // edges not yet removed
+    Counter updates;
+    Counter bloom_visits;
+    // Round state, indexed by round parity.  Phase A of round r derives its
+    // own entry from round r - 1's final counters (every block computes the
+    // same values; block 0 stores them for phase B and for round r + 1).
+    int32_t mode[2];    // kNormal or kGather
+    int32_t level[2];
+    int32_t cur[2];     // active-set buffer in use
+    int32_t gmin[2];    // gather rounds: minimum support above the level
+    int32_t done;
+    int32_t stall;
+    int32_t thresh;     // active threshold T
+    int32_t max_level;  // largest level at which edges were removed
+    u64 rounds, levels;
+};
+
+struct FrontItem {
+    int32_t e;
+    int32_t first;  // 1 for the edge's first chunk: assigns phi
+    uint32_t lo, hi;  // link positions of this chunk
+};
+
+struct BloomItem {
+    int32_t b;
+    int32_t nch;    // chunks of this bloom (the last one to finish finalizes)
+    uint32_t lo, hi;  // wedge range of this chunk
+};
+
+struct PeelArgs {
+    PeelCtl *ctl;
+    int32_t *sup;
+    int32_t *phi;
+    uint32_t *alive;
+    int32_t *bc;
+    int32_t *bk;
+    int32_t *bdone;
+    const uint32_t *bwoff;
+    const int32_t *wea;
+    const int32_t *web;
+    const int32_t *wbl;
+    const int64_t *link_off;
+    const uint32_t *link;
+    FrontItem *front[2];
+    BloomItem *tc[2];
+    int32_t *act[2];
+};
+
+// Each lane asks for `cnt` consecutive slots of *counter; one atomic per
+// wave.  Must be called by all 64 lanes.
+__device__ __forceinline__ u64 wave_alloc(uint32_t cnt, u64 *counter) {
+    const u64 inc = wave_inclusive_sum<u64>((u64)cnt);
+    const u64 total = __shfl(inc, kWave - 1, kWave);
+    u64 base = 0;
+    if (lane_id() == kWave - 1 && total) base = atomicAdd(counter, total);
+    base = __shfl(base, kWave - 1, kWave);
+    return base + inc - cnt;
 }
 
-// Phase A: one wave per frontier edge, lanes over its links.
-__global__ __launch_bounds__(kBlock) void k_phase_a(
-    const int32_t *front, PeelCtl *ctl, const int64_t *link_off, const uint32_t *link,
-    const int32_t *wea, const int32_t *web, const int32_t *wbl, uint32_t *alive,
-    const int32_t *bk, int32_t *bc, int32_t *touched, int32_t *sup, int32_t *phi,
-    int32_t *next) {
-    const int32_t nf = ctl->n_front;
-    const int32_t level = ctl->level;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    unsigned long long upd = 0;
-    for (int64_t i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < nf; i += waves) {
-        const int32_t e = front[i];
-        if (lane_id() == 0) phi[e] = level;
-        const int64_t a = link_off[e], b = link_off[(int64_t)e + 1];
-        for (int64_t j0 = a; j0 < b; j0 += kWave) {
-            const int64_t j = j0 + lane_id();
-            bool won = false;
-            int32_t blm = 0, twin = 0, d = 0;
-            if (j < b) {
-                const uint32_t w = link[j];
-                const uint32_t bit = 1u << (w & 31);
-                if (alive[w >> 5] & bit) {
-                    const uint32_t old = atomicAnd(&alive[w >> 5], ~bit);
-                    if (old & bit) {
-                        won = true;
-                        blm = wbl[w];
-                        const int32_t ea = wea[w];
-                        twin = ea == e ? web[w] : ea;
-                        d = bk[blm] - 1;
-                    }
+// Append frontier work items (chunks of the edge's links) where `take`.
+__device__ __forceinline__ void push_front(bool take, int32_t e, const PeelArgs &P, int q) {
+    uint32_t lo = 0, hi = 0, k = 0;
+    if (take) {
+        lo = (uint32_t)P.link_off[e];
+        hi = (uint32_t)P.link_off[(int64_t)e + 1];
+        k = hi - lo <= (uint32_t)kLinkChunk ? 1u : (hi - lo + kLinkChunk - 1) / kLinkChunk;
+    }
+    const u64 base = wave_alloc(k, &P.ctl->nf[q].v);
+    for (uint32_t c = 0; c < k; ++c) {
+        const uint32_t a = lo + c * kLinkChunk;
+        P.front[q][base + c] = FrontItem{e, c == 0 ? 1 : 0, a, min(a + (uint32_t)kLinkChunk, hi)};
+    }
+}
+
+// Lower supports by d where `active`; both atomics issue before either
+// result is used.  Crossings of the level go to the next frontier, of the
+// threshold to the active set.
+__device__ __forceinline__ void dec_support2(bool act1, int32_t e1, bool act2, int32_t e2,
+                                             int32_t d, int32_t level, int32_t thresh,
+                                             const PeelArgs &P, int q, int cur) {
+    int32_t o1 = 0, o2 = 0;
+    if (act1) o1 = atomicSub(&P.sup[e1], d);
+    if (act2) o2 = atomicSub(&P.sup[e2], d);
+    const bool f1 = act1 && o1 > level && o1 - d <= level;
+    const bool f2 = act2 && o2 > level && o2 - d <= level;
+    const bool a1 = act1 && o1 >= thresh && o1 - d < thresh;
+    const bool a2 = act2 && o2 >= thresh && o2 - d < thresh;
+    push_front(f1, e1, P, q);
+    push_front(f2, e2, P, q);
+    const u64 slot = wave_alloc((a1 ? 1u : 0u) + (a2 ? 1u : 0u), &P.ctl->na[cur].v);
+    if (a1) P.act[cur][slot] = e1;
+    if (a2) P.act[cur][slot + (a1 ? 1 : 0)] = e2;
+}
+
+// Phase A.  Decides the round, then: normal round, remove the frontier
+// edges' wedges; gather round (first round of a level), frontier = active
+// edges with support <= level, queued for the next round, while the active
+// set is compacted into the other buffer.
+__global__ __launch_bounds__(kBlock) void k_phase_a(PeelArgs P, int p) {
+    PeelCtl *C = P.ctl;
+    if (C->done | C->stall) return;
+    const int q = p ^ 1;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // Round r - 1's outputs are final: decide round r.
+    const int32_t pmode = C->mode[q], plevel = C->level[q], pcur = C->cur[q];
+    const int32_t pgmin = C->gmin[q];
+    const u64 nfp = C->nf[p].v;
+    const u64 rem = C->remaining.v;
+    const int cur = pmode == kGather ? pcur ^ 1 : pcur;
+    int32_t mode, level;
+    if (nfp > 0) {
+        mode = kNormal;
+        level = plevel;
+    } else if (pmode == kGather) {
+        if (pgmin == INT_MAX) {  // no active edge left
+            if (lead) {
+                if (rem == 0) C->done = 1;
+                else C->stall = 1;  // the host rebuilds the active set
+            }
+            return;
+        }
+        mode = kGather;
+        level = pgmin;  // jump to the smallest support the gather saw
+    } else {
+        if (rem == 0) {
+            if (lead) C->done = 1;
+            return;
+        }
+        mode = kGather;
+        level = plevel + 1;
+    }
+    if (lead) {
+        C->mode[p] = mode;
+        C->level[p] = level;
+        C->cur[p] = cur;
+        C->ntc[q].v = 0;
+        C->rounds += 1;
+        if (pmode == kGather && nfp > 0) C->levels += 1;
+        if (mode == kNormal && level > C->max_level) C->max_level = level;
+    }
+    const int32_t thresh = C->thresh;
+    const int64_t wid = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    if (mode == kGather) {
+        const int64_t na = (int64_t)C->na[cur].v;
+        int32_t mn = INT_MAX;
+        for (int64_t i0 = wid * kWave; i0 < na; i0 += nwaves * kWave) {
+            const int64_t i = i0 + lane_id();
+            bool take = false, keep = false;
+            int32_t e = 0;
+            if (i < na) {
+                e = P.act[cur][i];
+                if (P.phi[e] < 0) {
+                    const int32_t sv = P.sup[e];
+                    take = sv <= level;
+                    keep = !take;
+                    if (keep) mn = min(mn, sv);
                 }
             }
-            bool first = false;
-            if (won) first = atomicAdd(&bc[blm], 1) == 0;
-            wave_push(first, blm, touched, &ctl->n_touched);
-            dec_support(sup, twin, d, level, won && d > 0, next, &ctl->n_next);
-            upd += (won && d > 0) ? 1 : 0;
+            push_front(take, e, P, q);
+            const u64 slot = wave_alloc(keep ? 1u : 0u, &C->na[cur ^ 1].v);
+            if (keep) P.act[cur ^ 1][slot] = e;
         }
+        mn = wave_min(mn);
+        if (lane_id() == 0 && mn != INT_MAX) atomicMin(&C->gmin[p], mn);
+        return;
     }
-    upd = wave_sum(upd);
-    if (lane_id() == 0 && upd) atomicAdd(&ctl->updates, upd);
-}
-
-// Phase B: one wave per touched bloom, lanes over its wedge range.
-__global__ __launch_bounds__(kBlock) void k_phase_b(
-    const int32_t *touched, PeelCtl *ctl, const uint32_t *bwoff, const int32_t *wea,
-    const int32_t *web, uint32_t *alive, int32_t *bk, int32_t *bc, int32_t *sup,
-    int32_t *next) {
-    const int32_t nt = ctl->n_touched;
-    const int32_t level = ctl->level;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    unsigned long long upd = 0;
-    for (int64_t i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < nt; i += waves) {
-        const int32_t blm = touched[i];
-        const int32_t c = bc[blm];
-        const int32_t kn = bk[blm] - c;
-        const uint32_t w0 = bwoff[blm], w1 = bwoff[blm + 1];
-        if (kn > 0) {
-            for (uint32_t wb = w0; wb < w1; wb += kWave) {
-                const uint32_t w = wb + lane_id();
-                bool live = false;
-                if (w < w1) live = (alive[w >> 5] >> (w & 31)) & 1u;
-                dec_support(sup, live ? wea[w] : 0, c, level, live, next, &ctl->n_next);
-                dec_support(sup, live ? web[w] : 0, c, level, live, next, &ctl->n_next);
-                upd += live ? 2 : 0;
-                if (live && kn <= 1) atomicAnd(&alive[w >> 5], ~(1u << (w & 31)));
+    const int64_t nf = (int64_t)nfp;
+    u64 removed = 0, upd = 0;
+    for (int64_t i = wid; i < nf; i += nwaves) {
+        const FrontItem it = P.front[p][i];
+        const int32_t e = it.e;
+        if (it.first && lane_id() == 0) {
+            P.phi[e] = level;
+            removed += 1;
+        }
+        const uint32_t j = it.lo + lane_id();
+        bool won = false;
+        int32_t blm = 0, twin = 0, d = 0;
+        uint32_t w0 = 0, w1 = 0;
+        if (j < it.hi) {
+            const uint32_t w = P.link[j];
+            const uint32_t bit = 1u << (w & 31);
+            if (P.alive[w >> 5] & bit) {
+                blm = P.wbl[w];
+                const int32_t ea = P.wea[w], eb = P.web[w];
+                const uint32_t old = atomicAnd(&P.alive[w >> 5], ~bit);
+                const int32_t kb = P.bk[blm];
+                const uint32_t b0 = P.bwoff[blm], b1 = P.bwoff[blm + 1];
+                if (old & bit) {
+                    won = true;
+                    twin = ea == e ? eb : ea;
+                    d = kb - 1;
+                    w0 = b0;
+                    w1 = b1;
+                }
             }
         }
+        bool first = false;
+        if (won) first = atomicAdd(&P.bc[blm], 1) == 0;
+        const uint32_t nch = first ? (w1 - w0 + kWedgeChunk - 1) / kWedgeChunk : 0u;
+        const u64 cbase = wave_alloc(nch, &C->ntc[p].v);
+        for (uint32_t c = 0; c < nch; ++c) {
+            const uint32_t a = w0 + c * kWedgeChunk;
+            P.tc[p][cbase + c] = BloomItem{blm, (int32_t)nch, a, min(a + (uint32_t)kWedgeChunk, w1)};
+        }
+        dec_support2(won && d > 0, twin, false, 0, d, level, thresh, P, q, cur);
+        upd += (won && d > 0) ? 1 : 0;
+    }
+    removed = wave_sum(removed);
+    upd = wave_sum(upd);
+    if (lane_id() == 0) {
+        if (removed) atomicAdd(&C->remaining.v, (u64)(-(int64_t)removed));
+        if (upd) atomicAdd(&C->updates.v, upd);
+    }
+}
+
+// Phase B: survivors of every touched bloom lose C[B]; the last chunk of a
+// bloom to finish sets k[B] -= C[B], C[B] = 0.  Block 0 clears the counters
+// this round consumed (none of them is read here).
+__global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
+    PeelCtl *C = P.ctl;
+    if (C->done | C->stall) return;
+    const int q = p ^ 1;
+    const int32_t mode = C->mode[p];
+    const int32_t level = C->level[p];
+    const int cur = C->cur[p];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        C->nf[p].v = 0;
+        C->gmin[q] = INT_MAX;
+        if (mode == kGather) C->na[cur].v = 0;  // compacted into the other buffer
+    }
+    if (mode == kGather) return;
+    const int32_t thresh = C->thresh;
+    const int64_t ntc = (int64_t)C->ntc[p].v;
+    const int64_t wid = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    u64 upd = 0, visits = 0;
+    for (int64_t i = wid; i < ntc; i += nwaves) {
+        const BloomItem it = P.tc[p][i];
+        const int32_t b = it.b;
+        const uint32_t w = it.lo + lane_id();
+        const bool inr = w < it.hi;
+        const uint32_t word = inr ? P.alive[w >> 5] : 0u;
+        int32_t ea = 0, eb = 0;
+        if (inr) {
+            ea = P.wea[w];
+            eb = P.web[w];
+        }
+        const int32_t c = P.bc[b];
+        const int32_t kn = P.bk[b] - c;
+        const bool live = inr && kn > 0 && ((word >> (w & 31)) & 1u);
+        dec_support2(live, ea, live, eb, c, level, thresh, P, q, cur);
+        upd += live ? 2 : 0;
+        if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
         if (lane_id() == 0) {
-            bk[blm] = kn;
-            bc[blm] = 0;
+            if (atomicAdd(&P.bdone[b], 1) == it.nch - 1) {
+                P.bk[b] = kn;
+                P.bc[b] = 0;
+                P.bdone[b] = 0;
+                visits += 1;
+            }
         }
     }
     upd = wave_sum(upd);
-    if (lane_id() == 0 && upd) atomicAdd(&ctl->updates, upd);
-}
-
-// Round bookkeeping: next frontier becomes current; counts reset.
-__global__ void k_advance(PeelCtl *ctl) {
-    ctl->bloom_visits += (unsigned long long)ctl->n_touched;
-    ctl->n_front = ctl->n_next;
-    ctl->n_next = 0;
-    ctl->n_touched = 0;
-}
-
-__global__ __launch_bounds__(kBlock) void k_min_alive(const int32_t *sup, const int32_t *phi,
-                                                      int64_t m, PeelCtl *ctl) {
-    int32_t mn = INT_MAX;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x)
-        if (phi[e] < 0 && sup[e] < mn) mn = sup[e];
-    mn = wave_min(mn);
-    if (lane_id() == 0 && mn != INT_MAX) atomicMin(&ctl->min_sup, mn);
-}
-
-__global__ __launch_bounds__(kBlock) void k_gather(const int32_t *sup, const int32_t *phi,
-                                                   int64_t m, PeelCtl *ctl, int32_t *front) {
-    const int32_t mn = ctl->min_sup;
-    if (mn == INT_MAX) return;
-    const int32_t level = mn > ctl->level ? mn : ctl->level;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->pad = level;
-    for (int64_t e0 = blockIdx.x * (int64_t)blockDim.x; e0 < m;
-         e0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = e0 + threadIdx.x;
-        const bool take = e < m && phi[e] < 0 && sup[e] <= level;
-        wave_push(take, (int32_t)e, front, &ctl->n_front);
+    visits = wave_sum(visits);
+    if (lane_id() == 0) {
+        if (upd) atomicAdd(&C->updates.v, upd);
+        if (visits) atomicAdd(&C->bloom_visits.v, visits);
     }
 }
 
-__global__ void k_set_level(PeelCtl *ctl) {
-    ctl->level = ctl->pad;
-    ctl->min_sup = INT_MAX;
+// ---------------------------------------------------------------- refill
+
+__global__ __launch_bounds__(kBlock) void k_refill_compact(const int32_t *list, int64_t n,
+                                                           const int32_t *phi, const int32_t *sup,
+                                                           int32_t *out, u64 *nout,
+                                                           int32_t *min_out) {
+    int32_t mn = INT_MAX;
+    const int64_t nthr = (int64_t)gridDim.x * kBlock;
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~(kWave - 1)); i0 < n;
+         i0 += nthr) {
+        const int64_t i = i0 + lane_id();
+        bool keep = false;
+        int32_t e = 0;
+        if (i < n) {
+            e = list ? list[i] : (int32_t)i;
+            keep = phi[e] < 0;
+            if (keep) mn = min(mn, sup[e]);
+        }
+        const u64 slot = wave_alloc(keep ? 1u : 0u, nout);
+        if (keep) out[slot] = e;
+    }
+    mn = wave_min(mn);
+    if (lane_id() == 0 && mn != INT_MAX) atomicMin(min_out, mn);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refill_hist(const int32_t *list, int64_t n,
+                                                        const int32_t *sup, int32_t mn,
+                                                        u64 *hist) {
+    __shared__ u64 h[33];
+    if (threadIdx.x < 33) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const uint32_t d = (uint32_t)(sup[list[i]] - mn) + 1u;
+        atomicAdd(&h[31 - __clz(d)], 1ull);
+    }
+    __syncthreads();
+    if (threadIdx.x < 33 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refill_gather(const int32_t *list, int64_t n,
+                                                          const int32_t *sup, int32_t thresh,
+                                                          int32_t *act, u64 *na) {
+    const int64_t nthr = (int64_t)gridDim.x * kBlock;
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~(kWave - 1)); i0 < n;
+         i0 += nthr) {
+        const int64_t i = i0 + lane_id();
+        bool take = false;
+        int32_t e = 0;
+        if (i < n) {
+            e = list[i];
+            take = sup[e] < thresh;
+        }
+        const u64 slot = wave_alloc(take ? 1u : 0u, na);
+        if (take) act[slot] = e;
+    }
 }
 
 __global__ void k_init_peel(const uint64_t *supl, int64_t m, int32_t *sup, int32_t *phi,
@@ -190,70 +425,181 @@ __global__ void k_phi_out(const int32_t *phi, int64_t *out, int64_t m) {
         out[e] = phi[e];
 }
 
+// ----------------------------------------------------------- host side
+
+void launch_round(const PeelArgs &P, int p, hipStream_t s) {
+    k_phase_a<<<kGridA, kBlock, 0, s>>>(P, p);
+    k_phase_b<<<kGridB, kBlock, 0, s>>>(P, p);
+}
+
+// Captured chunks of `rounds` rounds, cached by argument bytes.
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    int rounds;
+    hipGraphExec_t exec;
+};
+std::vector<GraphEntry> &graph_cache() {
+    static std::vector<GraphEntry> *c = new std::vector<GraphEntry>();
+    return *c;
+}
+
+hipGraphExec_t chunk_graph(const PeelArgs &P, int rounds, hipStream_t s) {
+    std::vector<unsigned char> key(sizeof(PeelArgs));
+    std::memcpy(key.data(), &P, sizeof(PeelArgs));
+    auto &cache = graph_cache();
+    for (auto &g : cache)
+        if (g.rounds == rounds && g.key == key) return g.exec;
+    if (cache.size() >= 16) {
+        (void)hipGraphExecDestroy(cache.front().exec);
+        cache.erase(cache.begin());
+    }
+    hipStream_t cs;
+    BT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g;
+    BT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < rounds; ++r) launch_round(P, r & 1, cs);
+    BT_HIP(hipStreamEndCapture(cs, &g));
+    hipGraphExec_t ex;
+    BT_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    cache.push_back(GraphEntry{key, rounds, ex});
+    (void)s;
+    return ex;
+}
+
 }  // namespace
 
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s) {
     const int64_t m = r.m;
     if (m == 0) return;
-    int32_t *sup = ws.get<int32_t>("peel_sup", m);
-    int32_t *phi = ws.get<int32_t>("peel_phi", m);
-    int32_t *fa = ws.get<int32_t>("peel_front_a", m);
-    int32_t *fb = ws.get<int32_t>("peel_front_b", m);
-    int32_t *touched = ws.get<int32_t>("peel_touched", ix.n_b > 0 ? ix.n_b : 1);
-    int32_t *bc = ws.get<int32_t>("peel_bc", ix.n_b > 0 ? ix.n_b : 1);
-    uint32_t *alive = ws.get<uint32_t>("peel_alive", (ix.n_w + 31) / 32 + 1);
-    PeelCtl *ctl = ws.get<PeelCtl>("peel_ctl", 1);
+    if (2 * ix.n_w >= (int64_t)UINT32_MAX)
+        throw Error{BT_EOVERFLOW, "edge-to-wedge links must be below 2^32"};
+    const int64_t nb = ix.n_b > 0 ? ix.n_b : 1;
+    const int64_t words = (ix.n_w + 31) / 32 + 1;
+    const int64_t max_tc = nb + ix.n_w / kWedgeChunk + 1;
+    const int64_t max_front = m + 2 * ix.n_w / kLinkChunk + 1;
 
-    k_init_peel<<<grid_for(m, 256, 16384), 256, 0, s>>>(ix.supl, m, sup, phi, sup_out);
+    PeelArgs P{};
+    P.sup = ws.get<int32_t>("peel_sup", m);
+    P.phi = ws.get<int32_t>("peel_phi", m);
+    P.alive = ws.get<uint32_t>("peel_alive", words);
+    P.bc = ws.get<int32_t>("peel_bc", nb);
+    P.bdone = ws.get<int32_t>("peel_bdone", nb);
+    P.bk = ix.bk;
+    P.bwoff = ix.bwoff;
+    P.wea = ix.wea;
+    P.web = ix.web;
+    P.wbl = ix.wbl;
+    P.link_off = ix.link_off;
+    P.link = ix.link;
+    P.front[0] = ws.get<FrontItem>("peel_front0", max_front);
+    P.front[1] = ws.get<FrontItem>("peel_front1", max_front);
+    P.tc[0] = ws.get<BloomItem>("peel_tc0", max_tc);
+    P.tc[1] = ws.get<BloomItem>("peel_tc1", max_tc);
+    P.act[0] = ws.get<int32_t>("peel_act0", m);
+    P.act[1] = ws.get<int32_t>("peel_act1", m);
+    P.ctl = ws.get<PeelCtl>("peel_ctl", 1);
+    int32_t *glist[2] = {ws.get<int32_t>("peel_all0", m), ws.get<int32_t>("peel_all1", m)};
+    u64 *rs = ws.get<u64>("peel_refill", 40);  // [0] count, [1] min, [2..34] histogram
+
+    k_init_peel<<<grid_for(m, 256, 16384), 256, 0, s>>>(ix.supl, m, P.sup, P.phi, sup_out);
     BT_CHECK_LAUNCH();
-    k_init_alive<<<grid_for((ix.n_w + 31) / 32, 256, 16384), 256, 0, s>>>(ix.cursor, alive);
+    k_init_alive<<<grid_for(words, 256, 16384), 256, 0, s>>>(ix.cursor, P.alive);
     BT_CHECK_LAUNCH();
-    if (ix.n_b > 0) BT_HIP(hipMemsetAsync(bc, 0, sizeof(int32_t) * ix.n_b, s));
+    BT_HIP(hipMemsetAsync(P.bc, 0, sizeof(int32_t) * nb, s));
+    BT_HIP(hipMemsetAsync(P.bdone, 0, sizeof(int32_t) * nb, s));
     PeelCtl init{};
-    init.min_sup = INT_MAX;
-    BT_HIP(hipMemcpyAsync(ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
+    init.remaining.v = (u64)m;
+    init.gmin[0] = init.gmin[1] = INT_MAX;
+    BT_HIP(hipMemcpyAsync(P.ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
 
-    PeelCtl *hctl = reinterpret_cast<PeelCtl *>(host_scalars(8));
-    int64_t remaining = m;
-    int32_t *front = fa, *next = fb;
-    const int scan_grid = grid_for(m, kBlock, 4096);
-    while (remaining > 0) {
-        BT_HIP(hipMemcpyAsync(hctl, ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
-        BT_HIP(hipStreamSynchronize(s));
-        int32_t nf = hctl->n_front;
-        if (nf == 0) {
-            k_min_alive<<<scan_grid, kBlock, 0, s>>>(sup, phi, m, ctl);
+    PeelCtl *hc = reinterpret_cast<PeelCtl *>(host_scalars((int)(sizeof(PeelCtl) / 8 + 40)));
+    u64 *hr = reinterpret_cast<u64 *>(hc + 1);
+    const char *gv = std::getenv("BT_PEEL_GRAPH");
+    const bool use_graph = !(gv && std::atoi(gv) == 0);
+
+    int64_t n_all = m;
+    int cur = -1;  // -1: all edges, in id order
+    int chunk = 4;
+    bool need_refill = true;
+    for (int64_t guard = 0;; ++guard) {
+        if (need_refill) {
+            // Rebuild the active set: compact the remaining edges, find their
+            // minimum support, histogram supports above it, pick T so that
+            // the set holds a few percent of the remaining edges.
+            const int nxt = cur < 0 ? 0 : cur ^ 1;
+            BT_HIP(hipMemsetAsync(rs, 0, sizeof(u64) * 40, s));
+            fill_i32(reinterpret_cast<int32_t *>(rs + 1), INT_MAX, 1, s);
+            k_refill_compact<<<grid_for(n_all, kBlock, 4096), kBlock, 0, s>>>(
+                cur < 0 ? nullptr : glist[cur], n_all, P.phi, P.sup, glist[nxt], rs,
+                reinterpret_cast<int32_t *>(rs + 1));
             BT_CHECK_LAUNCH();
-            k_gather<<<scan_grid, kBlock, 0, s>>>(sup, phi, m, ctl, front);
-            BT_CHECK_LAUNCH();
-            k_set_level<<<1, 1, 0, s>>>(ctl);
-            BT_CHECK_LAUNCH();
-            BT_HIP(hipMemcpyAsync(hctl, ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+            BT_HIP(hipMemcpyAsync(hr, rs, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
             BT_HIP(hipStreamSynchronize(s));
-            nf = hctl->n_front;
-            if (nf == 0) break;  // nothing remains
-            ++pc.levels;
-            if (hctl->level > pc.max_phi) pc.max_phi = hctl->level;
+            cur = nxt;
+            n_all = (int64_t)hr[0];
+            if (n_all == 0) break;
+            const int32_t mn = *reinterpret_cast<int32_t *>(hr + 1);
+            k_refill_hist<<<grid_for(n_all, kBlock, 2048), kBlock, 0, s>>>(glist[cur], n_all,
+                                                                          P.sup, mn, rs + 2);
+            BT_CHECK_LAUNCH();
+            BT_HIP(hipMemcpyAsync(hr + 2, rs + 2, 33 * sizeof(u64), hipMemcpyDeviceToHost, s));
+            BT_HIP(hipStreamSynchronize(s));
+            const int64_t target = std::max<int64_t>(65536, n_all / 32);
+            int64_t thresh = INT_MAX, acc = 0;
+            for (int b = 0; b < 33; ++b) {
+                acc += (int64_t)hr[2 + b];
+                if (acc >= target) {
+                    thresh = std::min<int64_t>((int64_t)mn + (int64_t(2) << b) - 1, INT_MAX);
+                    break;
+                }
+            }
+            BT_HIP(hipMemsetAsync(&P.ctl->na[0].v, 0, sizeof(u64), s));
+            k_refill_gather<<<grid_for(n_all, kBlock, 4096), kBlock, 0, s>>>(
+                glist[cur], n_all, P.sup, (int32_t)thresh, P.act[0], &P.ctl->na[0].v);
+            BT_CHECK_LAUNCH();
+            // Round state back to a clean start: a gather round at the
+            // minimum remaining support.
+            BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+            BT_HIP(hipStreamSynchronize(s));
+            PeelCtl st = *hc;
+            // As if the previous round (parity 1) were a gather that found
+            // no frontier and saw minimum support mn in buffer 0.
+            st.nf[0].v = st.nf[1].v = st.ntc[0].v = st.ntc[1].v = 0;
+            st.na[1].v = 0;
+            st.mode[1] = kGather;
+            st.cur[1] = 1;
+            st.gmin[1] = mn;
+            st.gmin[0] = INT_MAX;
+            st.stall = 0;
+            st.thresh = (int32_t)thresh;
+            BT_HIP(hipMemcpyAsync(P.ctl, &st, sizeof st, hipMemcpyHostToDevice, s));
+            need_refill = false;
         }
-        ++pc.rounds;
-        remaining -= nf;
-        const int ga = grid_for((int64_t)nf * kWave, kBlock, 16384);
-        k_phase_a<<<ga, kBlock, 0, s>>>(front, ctl, ix.link_off, ix.link, ix.wea, ix.web, ix.wbl,
-                                         alive, ix.bk, bc, touched, sup, phi, next);
-        BT_CHECK_LAUNCH();
-        k_phase_b<<<16384, kBlock, 0, s>>>(touched, ctl, ix.bwoff, ix.wea, ix.web, alive, ix.bk,
-                                           bc, sup, next);
-        BT_CHECK_LAUNCH();
-        k_advance<<<1, 1, 0, s>>>(ctl);
-        BT_CHECK_LAUNCH();
-        std::swap(front, next);
+        if (use_graph) {
+            BT_HIP(hipGraphLaunch(chunk_graph(P, chunk, s), s));
+        } else {
+            for (int rr = 0; rr < chunk; ++rr) launch_round(P, rr & 1, s);
+            BT_CHECK_LAUNCH();
+        }
+        BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+        BT_HIP(hipStreamSynchronize(s));
+        if (hc->done) break;
+        if (hc->stall) need_refill = true;
+        chunk = std::min(chunk * 2, 64);
+        if (guard > 4 * m + 64) throw Error{BT_EDEVICE, "peel made no progress"};
     }
-    BT_HIP(hipMemcpyAsync(hctl, ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
-    pc.updates = (int64_t)hctl->updates;
-    pc.bloom_visits = (int64_t)hctl->bloom_visits;
-    k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(phi, phi_out, m);
+    pc.levels = (int64_t)hc->levels;
+    pc.rounds = (int64_t)hc->rounds;
+    pc.max_phi = hc->max_level;
+    pc.updates = (int64_t)hc->updates.v;
+    pc.bloom_visits = (int64_t)hc->bloom_visits.v;
+    if (hc->remaining.v != 0) throw Error{BT_EDEVICE, "peel ended with edges remaining"};
+    k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);
     BT_CHECK_LAUNCH();
 }
 
