@@ -38,6 +38,7 @@
 // round fills and the next consumes are double-buffered by round parity;
 // every counter is reset by a kernel that does not read it.
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -52,8 +53,14 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLinkChunk = kWave;   // links per phase-A work item (one per lane)
 constexpr int kWedgeChunk = kWave;  // wedges per phase-B work item (one per lane)
-constexpr int kGridA = 2048;
-constexpr int kGridB = 2048;
+int grid_a() {
+    static int g = std::getenv("BT_PEEL_GRID_A") ? std::atoi(std::getenv("BT_PEEL_GRID_A")) : 2048;
+    return g;
+}
+int grid_b() {
+    static int g = std::getenv("BT_PEEL_GRID_B") ? std::atoi(std::getenv("BT_PEEL_GRID_B")) : 2048;
+    return g;
+}
 
 typedef unsigned long long u64;
 
@@ -68,7 +75,6 @@ struct PeelCtl {
     Counter nf[2];      // frontier work items by round parity
     Counter ntc[2];     // bloom work items by round parity
     Counter na[2];      // active-set entries by buffer
-    Counter remaining;  // edges not yet removed
     Counter updates;
     Counter bloom_visits;
     // Round state, indexed by round parity.  Phase A of round r derives its
@@ -78,16 +84,17 @@ struct PeelCtl {
     int32_t level[2];
     int32_t cur[2];     // active-set buffer in use
     int32_t gmin[2];    // gather rounds: minimum support above the level
-    int32_t done;
     int32_t stall;
     int32_t thresh;     // active threshold T
     int32_t max_level;  // largest level at which edges were removed
+    int32_t pad;        // persistent kernel: parity of the next round
     u64 rounds, levels;
+    u64 prof[6];        // persistent kernel, BT_PEEL_PROFILE=1: block-0 clock ticks
 };
 
 struct FrontItem {
     int32_t e;
-    int32_t first;  // 1 for the edge's first chunk: assigns phi
+    int32_t first;    // 1 for the edge's first chunk: assigns phi
     uint32_t lo, hi;  // link positions of this chunk
 };
 
@@ -110,7 +117,7 @@ struct PeelArgs {
     const int32_t *web;
     const int32_t *wbl;
     const int64_t *link_off;
-    const uint32_t *link;
+    const uint2 *link;  // {wedge, bloom}
     FrontItem *front[2];
     BloomItem *tc[2];
     int32_t *act[2];
@@ -127,7 +134,7 @@ __device__ __forceinline__ u64 wave_alloc(uint32_t cnt, u64 *counter) {
     return base + inc - cnt;
 }
 
-// Append frontier work items (chunks of the edge's links) where `take`.
+// Append frontier work items (64-link chunks of edge e) where `take`.
 __device__ __forceinline__ void push_front(bool take, int32_t e, const PeelArgs &P, int q) {
     uint32_t lo = 0, hi = 0, k = 0;
     if (take) {
@@ -162,57 +169,65 @@ __device__ __forceinline__ void dec_support2(bool act1, int32_t e1, bool act2, i
     if (a2) P.act[cur][slot + (a1 ? 1 : 0)] = e2;
 }
 
-// Phase A.  Decides the round, then: normal round, remove the frontier
-// edges' wedges; gather round (first round of a level), frontier = active
-// edges with support <= level, queued for the next round, while the active
-// set is compacted into the other buffer.
-__global__ __launch_bounds__(kBlock) void k_phase_a(PeelArgs P, int p) {
-    PeelCtl *C = P.ctl;
-    if (C->done | C->stall) return;
+template <typename T> __device__ __forceinline__ T ld(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Round {
+    int32_t mode, level, cur;
+    u64 nf;  // frontier work items (normal rounds)
+};
+
+// Decide round r (parity p) from round r - 1's final counters.  Every
+// caller computes the same result; the lead stores it for phase B and for
+// round r + 1.  Returns false when the active set has run out (stall): the
+// host then rebuilds it, or finds that no edge remains.
+__device__ __forceinline__ bool decide_round(PeelCtl *C, int p, bool lead, Round &R) {
     const int q = p ^ 1;
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    // Round r - 1's outputs are final: decide round r.
-    const int32_t pmode = C->mode[q], plevel = C->level[q], pcur = C->cur[q];
-    const int32_t pgmin = C->gmin[q];
-    const u64 nfp = C->nf[p].v;
-    const u64 rem = C->remaining.v;
-    const int cur = pmode == kGather ? pcur ^ 1 : pcur;
-    int32_t mode, level;
+    const int32_t pmode = ld(&C->mode[q]), plevel = ld(&C->level[q]), pcur = ld(&C->cur[q]);
+    const int32_t pgmin = ld(&C->gmin[q]);
+    const u64 nfp = ld(&C->nf[p].v);
+    R.cur = pmode == kGather ? pcur ^ 1 : pcur;
+    R.nf = nfp;
     if (nfp > 0) {
-        mode = kNormal;
-        level = plevel;
+        R.mode = kNormal;
+        R.level = plevel;
     } else if (pmode == kGather) {
-        if (pgmin == INT_MAX) {  // no active edge left
-            if (lead) {
-                if (rem == 0) C->done = 1;
-                else C->stall = 1;  // the host rebuilds the active set
-            }
-            return;
+        if (pgmin == INT_MAX) {  // no active edge left (or none at all)
+            if (lead) C->stall = 1;
+            return false;
         }
-        mode = kGather;
-        level = pgmin;  // jump to the smallest support the gather saw
+        R.mode = kGather;
+        R.level = pgmin;  // jump to the smallest support the gather saw
     } else {
-        if (rem == 0) {
-            if (lead) C->done = 1;
-            return;
-        }
-        mode = kGather;
-        level = plevel + 1;
+        R.mode = kGather;
+        R.level = plevel + 1;
     }
     if (lead) {
-        C->mode[p] = mode;
-        C->level[p] = level;
-        C->cur[p] = cur;
+        C->mode[p] = R.mode;
+        C->level[p] = R.level;
+        C->cur[p] = R.cur;
         C->ntc[q].v = 0;
         C->rounds += 1;
         if (pmode == kGather && nfp > 0) C->levels += 1;
-        if (mode == kNormal && level > C->max_level) C->max_level = level;
+        if (R.mode == kNormal && R.level > C->max_level) C->max_level = R.level;
     }
+    return true;
+}
+
+// Phase A.  Normal round: remove the frontier edges' wedges.  Gather round
+// (first round of a level): frontier = active edges with support <= level,
+// queued for the next round, while the active set is compacted into the
+// other buffer.  Work is spread over waves [wid, +nwaves).
+__device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Round &R,
+                                             int64_t wid, int64_t nwaves, u64 &upd) {
+    PeelCtl *C = P.ctl;
+    const int q = p ^ 1;
+    const int32_t level = R.level;
+    const int cur = R.cur;
     const int32_t thresh = C->thresh;
-    const int64_t wid = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    if (mode == kGather) {
-        const int64_t na = (int64_t)C->na[cur].v;
+    if (R.mode == kGather) {
+        const int64_t na = (int64_t)ld(&C->na[cur].v);
         int32_t mn = INT_MAX;
         for (int64_t i0 = wid * kWave; i0 < na; i0 += nwaves * kWave) {
             const int64_t i = i0 + lane_id();
@@ -235,79 +250,87 @@ __global__ __launch_bounds__(kBlock) void k_phase_a(PeelArgs P, int p) {
         if (lane_id() == 0 && mn != INT_MAX) atomicMin(&C->gmin[p], mn);
         return;
     }
-    const int64_t nf = (int64_t)nfp;
-    u64 removed = 0, upd = 0;
-    for (int64_t i = wid; i < nf; i += nwaves) {
-        const FrontItem it = P.front[p][i];
+    const int64_t nf = (int64_t)R.nf;
+    int64_t i = wid;
+    FrontItem it{};
+    if (i < nf) it = P.front[p][i];
+    while (i < nf) {
+        const int64_t inext = i + nwaves;
+        FrontItem nx{};
+        if (inext < nf) nx = P.front[p][inext];  // next item, loaded early
         const int32_t e = it.e;
-        if (it.first && lane_id() == 0) {
-            P.phi[e] = level;
-            removed += 1;
-        }
+        if (it.first && lane_id() == 0) P.phi[e] = level;
         const uint32_t j = it.lo + lane_id();
+        const uint32_t l1 = it.hi;
         bool won = false;
         int32_t blm = 0, twin = 0, d = 0;
         uint32_t w0 = 0, w1 = 0;
-        if (j < it.hi) {
-            const uint32_t w = P.link[j];
+        if (j < l1) {
+            const uint2 lk = P.link[j];
+            const uint32_t w = lk.x;
+            blm = (int32_t)lk.y;
             const uint32_t bit = 1u << (w & 31);
-            if (P.alive[w >> 5] & bit) {
-                blm = P.wbl[w];
-                const int32_t ea = P.wea[w], eb = P.web[w];
-                const uint32_t old = atomicAnd(&P.alive[w >> 5], ~bit);
-                const int32_t kb = P.bk[blm];
-                const uint32_t b0 = P.bwoff[blm], b1 = P.bwoff[blm + 1];
-                if (old & bit) {
-                    won = true;
-                    twin = ea == e ? eb : ea;
-                    d = kb - 1;
-                    w0 = b0;
-                    w1 = b1;
-                }
+            const uint32_t old = atomicAnd(&P.alive[w >> 5], ~bit);
+            const int32_t ea = P.wea[w], eb = P.web[w];
+            const int32_t kb = P.bk[blm];
+            const uint32_t b0 = P.bwoff[blm], b1 = P.bwoff[blm + 1];
+            if (old & bit) {
+                won = true;
+                twin = ea == e ? eb : ea;
+                d = kb - 1;
+                w0 = b0;
+                w1 = b1;
             }
         }
+        // First kill in the bloom this round queues the bloom for phase B;
+        // the twin loses its k - 1 butterflies in the bloom.
         bool first = false;
+        int32_t otw = 0;
+        const bool dec = won && d > 0;
         if (won) first = atomicAdd(&P.bc[blm], 1) == 0;
+        if (dec) otw = atomicSub(&P.sup[twin], d);
         const uint32_t nch = first ? (w1 - w0 + kWedgeChunk - 1) / kWedgeChunk : 0u;
         const u64 cbase = wave_alloc(nch, &C->ntc[p].v);
         for (uint32_t c = 0; c < nch; ++c) {
             const uint32_t a = w0 + c * kWedgeChunk;
             P.tc[p][cbase + c] = BloomItem{blm, (int32_t)nch, a, min(a + (uint32_t)kWedgeChunk, w1)};
         }
-        dec_support2(won && d > 0, twin, false, 0, d, level, thresh, P, q, cur);
-        upd += (won && d > 0) ? 1 : 0;
-    }
-    removed = wave_sum(removed);
-    upd = wave_sum(upd);
-    if (lane_id() == 0) {
-        if (removed) atomicAdd(&C->remaining.v, (u64)(-(int64_t)removed));
-        if (upd) atomicAdd(&C->updates.v, upd);
+        const bool tf = dec && otw > level && otw - d <= level;
+        const bool ta = dec && otw >= thresh && otw - d < thresh;
+        push_front(tf, twin, P, q);
+        const u64 slot = wave_alloc(ta ? 1u : 0u, &C->na[cur].v);
+        if (ta) P.act[cur][slot] = twin;
+        upd += dec ? 1 : 0;
+        it = nx;
+        i = inext;
     }
 }
 
 // Phase B: survivors of every touched bloom lose C[B]; the last chunk of a
-// bloom to finish sets k[B] -= C[B], C[B] = 0.  Block 0 clears the counters
-// this round consumed (none of them is read here).
-__global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
+// bloom to finish sets k[B] -= C[B], C[B] = 0.  The lead clears counters
+// this round consumed (none of them is read in this phase).
+__device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Round &R,
+                                             int64_t wid, int64_t nwaves, bool lead, u64 &upd,
+                                             u64 &visits) {
     PeelCtl *C = P.ctl;
-    if (C->done | C->stall) return;
     const int q = p ^ 1;
-    const int32_t mode = C->mode[p];
-    const int32_t level = C->level[p];
-    const int cur = C->cur[p];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int32_t level = R.level;
+    const int cur = R.cur;
+    if (lead) {
         C->nf[p].v = 0;
         C->gmin[q] = INT_MAX;
-        if (mode == kGather) C->na[cur].v = 0;  // compacted into the other buffer
+        if (R.mode == kGather) C->na[cur].v = 0;  // compacted into the other buffer
     }
-    if (mode == kGather) return;
+    if (R.mode == kGather) return;
     const int32_t thresh = C->thresh;
-    const int64_t ntc = (int64_t)C->ntc[p].v;
-    const int64_t wid = blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    u64 upd = 0, visits = 0;
-    for (int64_t i = wid; i < ntc; i += nwaves) {
-        const BloomItem it = P.tc[p][i];
+    const int64_t ntc = (int64_t)ld(&C->ntc[p].v);
+    int64_t i = wid;
+    BloomItem it{};
+    if (i < ntc) it = P.tc[p][i];
+    while (i < ntc) {
+        const int64_t inext = i + nwaves;
+        BloomItem nx{};
+        if (inext < ntc) nx = P.tc[p][inext];  // next item, loaded early
         const int32_t b = it.b;
         const uint32_t w = it.lo + lane_id();
         const bool inr = w < it.hi;
@@ -324,19 +347,150 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
         upd += live ? 2 : 0;
         if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
         if (lane_id() == 0) {
-            if (atomicAdd(&P.bdone[b], 1) == it.nch - 1) {
+            if (it.nch == 1 || atomicAdd(&P.bdone[b], 1) == it.nch - 1) {
                 P.bk[b] = kn;
                 P.bc[b] = 0;
                 P.bdone[b] = 0;
                 visits += 1;
             }
         }
+        it = nx;
+        i = inext;
     }
+}
+
+// Adds per-lane statistics to the control block (one atomic per wave).
+__device__ __forceinline__ void flush_stats(PeelCtl *C, u64 upd, u64 visits) {
     upd = wave_sum(upd);
     visits = wave_sum(visits);
     if (lane_id() == 0) {
         if (upd) atomicAdd(&C->updates.v, upd);
         if (visits) atomicAdd(&C->bloom_visits.v, visits);
+    }
+}
+
+// --- one kernel per phase (rounds replayed from a captured HIP graph) ---
+
+__global__ __launch_bounds__(kBlock) void k_phase_a(PeelArgs P, int p) {
+    PeelCtl *C = P.ctl;
+    if (C->stall) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    Round R;
+    if (!decide_round(C, p, lead, R)) return;
+    u64 upd = 0;
+    phase_a_work(P, p, R, blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave,
+                 (int64_t)gridDim.x * kWavesPerBlock, upd);
+    flush_stats(C, upd, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
+    PeelCtl *C = P.ctl;
+    if (C->stall) return;
+    Round R;
+    R.mode = C->mode[p];
+    R.level = C->level[p];
+    R.cur = C->cur[p];
+    R.nf = 0;
+    u64 upd = 0, visits = 0;
+    phase_b_work(P, p, R, blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave,
+                 (int64_t)gridDim.x * kWavesPerBlock, blockIdx.x == 0 && threadIdx.x == 0, upd,
+                 visits);
+    flush_stats(C, upd, visits);
+}
+
+// --- persistent cooperative kernel: rounds separated by grid barriers ---
+
+constexpr int kPBlock = 512;
+
+struct GridBar {
+    Counter group[8];
+    Counter top;
+    Counter gen;
+    int32_t fail;
+};
+
+// Two-level barrier: blocks arrive at one of eight group counters, the last
+// of each group at the top counter, and the last of those opens the next
+// generation.  Release and acquire fences make every block's writes before
+// the barrier visible to every block after it.  A waiter gives up after a
+// bounded spin (the kernel then stops with `fail` set) so no bug can hang
+// the device.
+__device__ bool grid_sync(GridBar *B, u64 &gen_local) {
+    __shared__ int ok_s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        const unsigned nb = gridDim.x;
+        const unsigned g = blockIdx.x & 7;
+        const unsigned ngroups = nb < 8 ? nb : 8;
+        const unsigned gsize = (nb - g + 7) / 8;
+        bool opener = false;
+        if (atomicAdd(&B->group[g].v, 1ull) == gsize - 1) {
+            __hip_atomic_store(&B->group[g].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            if (atomicAdd(&B->top.v, 1ull) == ngroups - 1) {
+                __hip_atomic_store(&B->top.v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+                atomicAdd(&B->gen.v, 1ull);
+                opener = true;
+            }
+        }
+        if (!opener) {
+            int64_t spins = 0;
+            while (ld(&B->gen.v) == gen_local) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (int64_t(1) << 23) || ld(&B->fail)) {
+                    __hip_atomic_store(&B->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        gen_local += 1;
+        __threadfence();
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+__global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar *B,
+                                                             int64_t max_rounds, int prof) {
+    PeelCtl *C = P.ctl;
+    u64 gen_local = 0;
+    if (threadIdx.x == 0) gen_local = ld(&B->gen.v);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const int64_t wid = blockIdx.x * (int64_t)(kPBlock / kWave) + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
+    int p = 0;
+    u64 t[5] = {0, 0, 0, 0, 0}, acc[6] = {0, 0, 0, 0, 0, 0};
+    u64 upd = 0, visits = 0;
+    for (int64_t r = 0; r < max_rounds; ++r) {
+        if (prof && lead) t[0] = wall_clock64();
+        Round R;
+        if (!decide_round(C, p, lead, R)) break;
+        phase_a_work(P, p, R, wid, nwaves, upd);
+        if (prof && lead) t[1] = wall_clock64();
+        if (!grid_sync(B, gen_local)) break;
+        if (prof && lead) t[2] = wall_clock64();
+        phase_b_work(P, p, R, wid, nwaves, lead, upd, visits);
+        if (prof && lead) t[3] = wall_clock64();
+        if (!grid_sync(B, gen_local)) break;
+        if (prof && lead) {
+            t[4] = wall_clock64();
+            for (int k = 0; k < 4; ++k) acc[k] += t[k + 1] - t[k];
+            if (R.mode == kGather) {
+                acc[4] += t[2] - t[0];
+                acc[5] += 1;
+            }
+        }
+        p ^= 1;
+    }
+    flush_stats(C, upd, visits);
+    if (lead) {
+        C->pad = p;
+        for (int k = 0; k < 6; ++k) C->prof[k] += acc[k];
     }
 }
 
@@ -428,8 +582,8 @@ __global__ void k_phi_out(const int32_t *phi, int64_t *out, int64_t m) {
 // ----------------------------------------------------------- host side
 
 void launch_round(const PeelArgs &P, int p, hipStream_t s) {
-    k_phase_a<<<kGridA, kBlock, 0, s>>>(P, p);
-    k_phase_b<<<kGridB, kBlock, 0, s>>>(P, p);
+    k_phase_a<<<grid_a(), kBlock, 0, s>>>(P, p);
+    k_phase_b<<<grid_b(), kBlock, 0, s>>>(P, p);
 }
 
 // Captured chunks of `rounds` rounds, cached by argument bytes.
@@ -511,14 +665,29 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     BT_HIP(hipMemsetAsync(P.bc, 0, sizeof(int32_t) * nb, s));
     BT_HIP(hipMemsetAsync(P.bdone, 0, sizeof(int32_t) * nb, s));
     PeelCtl init{};
-    init.remaining.v = (u64)m;
     init.gmin[0] = init.gmin[1] = INT_MAX;
     BT_HIP(hipMemcpyAsync(P.ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
 
     PeelCtl *hc = reinterpret_cast<PeelCtl *>(host_scalars((int)(sizeof(PeelCtl) / 8 + 40)));
     u64 *hr = reinterpret_cast<u64 *>(hc + 1);
+    // BT_PEEL_MODE=graph replays captured two-kernel rounds instead of the
+    // persistent kernel; BT_PEEL_GRAPH=0 launches those rounds directly.
+    const char *mv = std::getenv("BT_PEEL_MODE");
+    const bool persistent = !(mv && std::strcmp(mv, "graph") == 0);
     const char *gv = std::getenv("BT_PEEL_GRAPH");
     const bool use_graph = !(gv && std::atoi(gv) == 0);
+    GridBar *bar = ws.get<GridBar>("peel_bar", 1);
+    BT_HIP(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
+    int pblocks = 0;
+    if (persistent) {
+        int dev = 0, cus = 0, occ = 0;
+        BT_HIP(hipGetDevice(&dev));
+        BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_persistent, kPBlock, 0));
+        const char *pb = std::getenv("BT_PEEL_PBLOCKS");
+        pblocks = pb ? std::atoi(pb) : 128;
+        pblocks = std::max(1, std::min(pblocks, occ * cus));
+    }
 
     int64_t n_all = m;
     int cur = -1;  // -1: all edges, in id order
@@ -578,7 +747,13 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             BT_HIP(hipMemcpyAsync(P.ctl, &st, sizeof st, hipMemcpyHostToDevice, s));
             need_refill = false;
         }
-        if (use_graph) {
+        if (persistent) {
+            int64_t max_rounds = 4 * m + 64;
+            int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
+            void *args[] = {&P, &bar, &max_rounds, &prof};
+            BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
+                                              dim3(kPBlock), args, 0, s));
+        } else if (use_graph) {
             BT_HIP(hipGraphLaunch(chunk_graph(P, chunk, s), s));
         } else {
             for (int rr = 0; rr < chunk; ++rr) launch_round(P, rr & 1, s);
@@ -586,7 +761,12 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         }
         BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
         BT_HIP(hipStreamSynchronize(s));
-        if (hc->done) break;
+        if (persistent) {
+            int32_t fail = 0;
+            BT_HIP(hipMemcpy(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost));
+            if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
+            if (!hc->stall) throw Error{BT_EDEVICE, "peel stopped early"};
+        }
         if (hc->stall) need_refill = true;
         chunk = std::min(chunk * 2, 64);
         if (guard > 4 * m + 64) throw Error{BT_EDEVICE, "peel made no progress"};
@@ -598,7 +778,10 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     pc.max_phi = hc->max_level;
     pc.updates = (int64_t)hc->updates.v;
     pc.bloom_visits = (int64_t)hc->bloom_visits.v;
-    if (hc->remaining.v != 0) throw Error{BT_EDEVICE, "peel ended with edges remaining"};
+    if (std::getenv("BT_PEEL_PROFILE"))
+        std::fprintf(stderr, "[peel] rounds %llu  block0 us: phaseA %.0f bar1 %.0f phaseB %.0f bar2 %.0f; gather rounds %llu phaseA+bar1 %.0f\n",
+                     hc->rounds, hc->prof[0] / 100.0, hc->prof[1] / 100.0, hc->prof[2] / 100.0,
+                     hc->prof[3] / 100.0, hc->prof[5], hc->prof[4] / 100.0);
     k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);
     BT_CHECK_LAUNCH();
 }
