@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--cpu-frac", type=float, default=0.3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="chunglu5m", choices=["chunglu5m", "uniform10k", "hub20m"])
+    ap.add_argument("--batch", type=int, default=512,
+                    help="graphs of the many-small-graphs pool for the batched-vs-plain line (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -131,10 +133,40 @@ def main():
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None},
     }
+    if args.batch > 0:
+        out["batched"] = batch_compare(args.batch)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_frac)
     print(json.dumps(out), flush=True)
+
+
+def batch_compare(n):
+    """Graphs/s of the batched form against the plain per-graph loop (same graphs)."""
+    import torch
+    from paper_2001_06111_amd import binding, synth
+    gs = [synth.batch_graph(i) for i in range(n)]
+    dgs = [binding.DeviceGraph.upload(g, "cuda:0") for g in gs]
+    m = sum(g.m for g in gs)
+    binding.bt_decompose_batch(dgs[:8])
+    binding.bt_decompose(dgs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [binding.bt_decompose(d)[1] for d in dgs]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, phis, st = binding.bt_decompose_batch(dgs, stats=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(plain, phis))
+    print(f"[bench] batch of {n}: plain {t_plain:.3f}s batched {t_batch:.3f}s same={same}",
+          file=sys.stderr, flush=True)
+    return {"workload": f"first {n} graphs of the 4096-graph pool", "graphs": n, "edges": m,
+            "plain_graphs_per_s": n / t_plain, "batched_graphs_per_s": n / t_batch,
+            "plain_edges_per_s": m / t_plain, "batched_edges_per_s": m / t_batch,
+            "speedup": t_plain / t_batch, "batched_equals_plain": same,
+            "batched_rounds": st["rounds"]}
 
 
 def wedge_bytes(st, m):

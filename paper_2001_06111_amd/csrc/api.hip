@@ -122,6 +122,198 @@ void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
     ix.n_w = (int64_t)(c & 0xffffffffu);
 }
 
+void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const PeelCounters &pc,
+                int64_t m, int64_t butterflies, Events &ev) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->butterflies = butterflies;
+    stats->wedges_po = r.wedges_po;
+    stats->blooms = ix.n_b;
+    stats->bloom_wedges = ix.n_w;
+    stats->index_bytes = index_bytes(ix, m);
+    stats->levels = pc.levels;
+    stats->rounds = pc.rounds;
+    stats->max_phi = pc.max_phi;
+    stats->support_updates = pc.updates;
+    stats->bloom_visits = pc.bloom_visits;
+    stats->ms_prepare = ev.ms(0, 1);
+    stats->ms_count = ev.ms(1, 2);
+    stats->ms_link = ev.ms(2, 3);
+    stats->ms_peel = ev.ms(3, 4);
+}
+
+void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
+                    Workspace &ws, hipStream_t stream) {
+    Events ev(stats != nullptr, stream);
+    ev.mark(0);
+    RankCSR r;
+    IndexArrays ix;
+    build_all(g, r, ix, false, nullptr, ws, stream, &ev);
+    ev.mark(3);
+    PeelCounters pc;
+    peel(r, ix, sup_out, phi_out, pc, ws, stream);
+    ev.mark(4);
+    int64_t *hs = host_scalars(2);
+    BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    BT_HIP(hipStreamSynchronize(stream));
+    if (stats) fill_stats(stats, r, ix, pc, g.m, hs[0], ev);
+}
+
+// ---- batches: many graphs decomposed as one disjoint union --------------
+// A butterfly never spans two connected components, so the supports and
+// bitruss numbers of a disjoint union are those of its parts, and the
+// union's vertex order restricted to one part is that part's own priority
+// order (degrees are local; ids keep their order within each layer).  One
+// pipeline run therefore serves every graph of a batch, and each peel
+// round advances all of them together.
+
+struct BatchEntry {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    int64_t *sup_out;
+    int64_t *phi_out;
+    int32_t nu, nl;
+    int64_t m;
+    int64_t nu_off, nl_off, m_off;
+};
+
+// Union CSR: rows and ids shifted by the graph's offsets.  Each graph's own
+// bounds are checked here (the union check cannot see ids that stray into a
+// neighbouring graph's range); values are only copied, never used to index.
+__global__ void k_batch_union(const BatchEntry *tab, int32_t ng, int64_t *row_ptr_u,
+                              int32_t *col_u, int32_t *flags) {
+    for (int32_t gi = blockIdx.y; gi < ng; gi += gridDim.y) {
+        const BatchEntry E = tab[gi];
+        int32_t bad = 0;
+        const int64_t span = E.m > (int64_t)E.nu + 1 ? E.m : (int64_t)E.nu + 1;
+        for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < span;
+             k += (int64_t)gridDim.x * blockDim.x) {
+            if (k <= E.nu) {
+                const int64_t v = E.row_ptr[k];
+                if (v < 0 || v > E.m || (k == 0 && v != 0) || (k == E.nu && v != E.m)) bad = 1;
+                if (k < E.nu && E.row_ptr[k + 1] < v) bad = 1;
+                if (k < E.nu) row_ptr_u[E.nu_off + k] = E.m_off + v;
+            }
+            if (k < E.m) {
+                const int32_t c = E.col[k];
+                if (c < 0 || c >= E.nl) bad = 1;
+                col_u[E.m_off + k] = (int32_t)(E.nl_off + c);
+            }
+        }
+        if (bad) atomicOr(flags, 1);
+    }
+}
+
+__global__ void k_batch_scatter(const BatchEntry *tab, int32_t ng, const int64_t *sup_u,
+                                const int64_t *phi_u) {
+    for (int32_t gi = blockIdx.y; gi < ng; gi += gridDim.y) {
+        const BatchEntry E = tab[gi];
+        for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < E.m;
+             k += (int64_t)gridDim.x * blockDim.x) {
+            if (E.sup_out) E.sup_out[k] = sup_u[E.m_off + k];
+            E.phi_out[k] = phi_u[E.m_off + k];
+        }
+    }
+}
+
+void add_stats(bt_stats &t, const bt_stats &s) {
+    t.butterflies += s.butterflies;
+    t.wedges_po += s.wedges_po;
+    t.blooms += s.blooms;
+    t.bloom_wedges += s.bloom_wedges;
+    t.index_bytes = std::max(t.index_bytes, s.index_bytes);
+    t.levels += s.levels;
+    t.rounds += s.rounds;
+    t.max_phi = std::max(t.max_phi, s.max_phi);
+    t.support_updates += s.support_updates;
+    t.bloom_visits += s.bloom_visits;
+    t.ms_prepare += s.ms_prepare;
+    t.ms_count += s.ms_count;
+    t.ms_link += s.ms_link;
+    t.ms_peel += s.ms_peel;
+}
+
+// Graphs [a, b) as one union; splits the range if the union is too large.
+void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out,
+                 int64_t *const *phi_out, bt_stats *stats, Workspace &ws, hipStream_t s) {
+    std::vector<BatchEntry> tab(b - a);
+    int64_t nu = 0, nl = 0, m = 0, max_span = 1;
+    for (int32_t i = a; i < b; ++i) {
+        BatchEntry &E = tab[i - a];
+        E.row_ptr = gs[i].row_ptr;
+        E.col = gs[i].col;
+        E.sup_out = sup_out ? sup_out[i] : nullptr;
+        E.phi_out = phi_out[i];
+        E.nu = gs[i].n_upper;
+        E.nl = gs[i].n_lower;
+        E.m = gs[i].m;
+        E.nu_off = nu;
+        E.nl_off = nl;
+        E.m_off = m;
+        nu += E.nu;
+        nl += E.nl;
+        m += E.m;
+        max_span = std::max<int64_t>(max_span, std::max<int64_t>(E.m, (int64_t)E.nu + 1));
+    }
+    const bool splittable = b - a > 1;
+    if (splittable && (nu + nl >= INT32_MAX || m >= INT32_MAX)) {
+        const int32_t mid = a + (b - a) / 2;
+        batch_range(gs, a, mid, sup_out, phi_out, stats, ws, s);
+        batch_range(gs, mid, b, sup_out, phi_out, stats, ws, s);
+        return;
+    }
+    BatchEntry *dtab = ws.get<BatchEntry>("batch_tab", b - a);
+    int64_t *row_ptr_u = ws.get<int64_t>("batch_rowptr", nu + 1);
+    int32_t *col_u = ws.get<int32_t>("batch_col", m);
+    int32_t *flags = ws.get<int32_t>("batch_flags", 1);
+    int64_t *sup_u = ws.get<int64_t>("batch_sup", m);
+    int64_t *phi_u = ws.get<int64_t>("batch_phi", m);
+    BT_HIP(hipMemcpyAsync(dtab, tab.data(), sizeof(BatchEntry) * tab.size(),
+                          hipMemcpyHostToDevice, s));
+    BT_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    fill_i64(row_ptr_u + nu, m, 1, s);
+    const dim3 grid((unsigned)std::min<int64_t>(ceil_div(max_span, 256), 64),
+                    (unsigned)std::min<int32_t>(b - a, 65535));
+    k_batch_union<<<grid, 256, 0, s>>>(dtab, b - a, row_ptr_u, col_u, flags);
+    BT_CHECK_LAUNCH();
+    int32_t hf = 0;
+    BT_HIP(hipMemcpyAsync(&hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
+    BT_HIP(hipStreamSynchronize(s));
+    if (hf) throw Error{BT_EINVAL, "a graph of the batch is malformed"};
+    const bt_csr u{(int32_t)nu, (int32_t)nl, m, row_ptr_u, col_u};
+    bt_stats st;
+    try {
+        decompose_impl(u, sup_u, phi_u, stats ? &st : nullptr, ws, s);
+    } catch (const Error &e) {
+        if (e.status != BT_EOVERFLOW || !splittable) throw;
+        const int32_t mid = a + (b - a) / 2;
+        batch_range(gs, a, mid, sup_out, phi_out, stats, ws, s);
+        batch_range(gs, mid, b, sup_out, phi_out, stats, ws, s);
+        return;
+    }
+    k_batch_scatter<<<grid, 256, 0, s>>>(dtab, b - a, sup_u, phi_u);
+    BT_CHECK_LAUNCH();
+    BT_HIP(hipStreamSynchronize(s));
+    if (stats) add_stats(*stats, st);
+}
+
+// Batches are cut at about kBatchEdges edges so that each union stays well
+// inside the index limits; an oversized union is split in halves.
+constexpr int64_t kBatchEdges = int64_t(1) << 25;
+
+void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
+                          int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
+                          hipStream_t s) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    int32_t a = 0;
+    while (a < n) {
+        int32_t b = a;
+        int64_t m = 0;
+        while (b < n && (b == a || m + gs[b].m <= kBatchEdges)) m += gs[b++].m;
+        batch_range(gs, a, b, sup_out, phi_out, stats, ws, s);
+        a = b;
+    }
+}
+
 }  // namespace
 
 }  // namespace bt
@@ -253,74 +445,22 @@ bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out, bt_s
         check_graph(g);
         if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
         std::lock_guard<std::mutex> lk(lib().mu);
-        Workspace &ws = lib().ws;
-        Events ev(stats != nullptr, stream);
-        ev.mark(0);
-        RankCSR r;
-        IndexArrays ix;
-        build_all(*g, r, ix, false, nullptr, ws, stream, &ev);
-        ev.mark(3);
-        PeelCounters pc;
-        peel(r, ix, sup_out, phi_out, pc, ws, stream);
-        ev.mark(4);
-        if (stats) {
-            int64_t *hs = host_scalars(2);
-            BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost,
-                                  stream));
-            BT_HIP(hipStreamSynchronize(stream));
-            std::memset(stats, 0, sizeof *stats);
-            stats->butterflies = hs[0];
-            stats->wedges_po = r.wedges_po;
-            stats->blooms = ix.n_b;
-            stats->bloom_wedges = ix.n_w;
-            stats->index_bytes = index_bytes(ix, g->m);
-            stats->levels = pc.levels;
-            stats->rounds = pc.rounds;
-            stats->max_phi = pc.max_phi;
-            stats->support_updates = pc.updates;
-            stats->bloom_visits = pc.bloom_visits;
-            stats->ms_prepare = ev.ms(0, 1);
-            stats->ms_count = ev.ms(1, 2);
-            stats->ms_link = ev.ms(2, 3);
-            stats->ms_peel = ev.ms(3, 4);
-        } else {
-            BT_HIP(hipStreamSynchronize(stream));
-        }
+        decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream);
     });
 }
 
 bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const *sup_out,
                              int64_t *const *phi_out, bt_stats *stats, hipStream_t stream) {
-    if (n_graphs < 0 || (n_graphs > 0 && (!gs || !phi_out))) {
-        set_error("invalid batch arguments");
-        return BT_EINVAL;
-    }
-    bt_stats total;
-    std::memset(&total, 0, sizeof total);
-    for (int32_t i = 0; i < n_graphs; ++i) {
-        bt_stats st;
-        bt_status rc = bt_decompose(&gs[i], sup_out ? sup_out[i] : nullptr, phi_out[i],
-                                    stats ? &st : nullptr, stream);
-        if (rc != BT_OK) return rc;
-        if (stats) {
-            total.butterflies += st.butterflies;
-            total.wedges_po += st.wedges_po;
-            total.blooms += st.blooms;
-            total.bloom_wedges += st.bloom_wedges;
-            total.index_bytes += st.index_bytes;
-            total.levels = std::max(total.levels, st.levels);
-            total.rounds = std::max(total.rounds, st.rounds);
-            total.max_phi = std::max(total.max_phi, st.max_phi);
-            total.support_updates += st.support_updates;
-            total.bloom_visits += st.bloom_visits;
-            total.ms_prepare += st.ms_prepare;
-            total.ms_count += st.ms_count;
-            total.ms_link += st.ms_link;
-            total.ms_peel += st.ms_peel;
+    return guard([&] {
+        if (n_graphs < 0 || (n_graphs > 0 && (!gs || !phi_out)))
+            throw Error{BT_EINVAL, "invalid batch arguments"};
+        for (int32_t i = 0; i < n_graphs; ++i) {
+            check_graph(&gs[i]);
+            if (gs[i].m > 0 && !phi_out[i]) throw Error{BT_EINVAL, "phi_out[i] is NULL"};
         }
-    }
-    if (stats) *stats = total;
-    return BT_OK;
+        std::lock_guard<std::mutex> lk(lib().mu);
+        decompose_batch_impl(gs, n_graphs, sup_out, phi_out, stats, lib().ws, stream);
+    });
 }
 
 }  // extern "C"

@@ -685,7 +685,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_persistent, kPBlock, 0));
         const char *pb = std::getenv("BT_PEEL_PBLOCKS");
-        pblocks = pb ? std::atoi(pb) : 128;
+        pblocks = pb ? std::atoi(pb) : 96;
         pblocks = std::max(1, std::min(pblocks, occ * cus));
     }
 

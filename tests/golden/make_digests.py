@@ -1,0 +1,81 @@
+"""Write tests/golden/digests.json from the CPU oracle.
+
+For each seeded workload: SHA-256 of the oracle's int64 supports and int64
+bitruss numbers (little-endian, edge order = CSR position), the butterfly
+total and the generator version.  For the many-small-graphs pool the
+digest covers the concatenation of the per-graph arrays in pool order.
+Calls only `oracle` and the seeded generators.
+
+  python tests/golden/make_digests.py [uniform10k] [chunglu5m] [pool:N] [big:N]
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2001_06111_amd import synth  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "digests.json")
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
+
+
+def run(g):
+    t0 = time.time()
+    sup, bf, pairs = oracle.support(g.n_upper, g.n_lower, g.row_ptr, g.col)
+    assert bf == pairs
+    phi, st = oracle.bitruss(g.n_upper, g.n_lower, g.row_ptr, g.col, sup=sup)
+    return sup, bf, phi, st, time.time() - t0
+
+
+def main(args):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for a in args:
+        if a in ("uniform10k", "chunglu5m", "hub20m"):
+            g = {"uniform10k": synth.plain_uniform_10k, "chunglu5m": synth.plain_chunglu_5m,
+                 "hub20m": synth.plain_hub_20m}[a]()
+            sup, bf, phi, st, dt = run(g)
+            data[g.name] = {"m": g.m, "butterflies": bf, "sup_sha256": sha(sup),
+                            "phi_sha256": sha(phi), "max_phi": int(phi.max()) if g.m else 0,
+                            "levels": st["levels"], "rounds": st["rounds"],
+                            "oracle_seconds": round(dt, 1), "oracle_threads": oracle.max_threads(),
+                            "generator_version": synth.GENERATOR_VERSION}
+        elif a.startswith("pool:") or a.startswith("big:"):
+            kind, n = a.split(":")
+            n = int(n)
+            hs, hp = hashlib.sha256(), hashlib.sha256()
+            m_tot = bf_tot = 0
+            t0 = time.time()
+            per = []
+            for i in range(n):
+                g = synth.batch_graph(i) if kind == "pool" else synth.big_serving_graph(i)
+                sup, bf, phi, _, _ = run(g)
+                hs.update(np.ascontiguousarray(sup, dtype="<i8").tobytes())
+                hp.update(np.ascontiguousarray(phi, dtype="<i8").tobytes())
+                m_tot += g.m
+                bf_tot += bf
+                per.append({"m": g.m, "butterflies": bf, "phi_sha256": sha(phi)})
+                print(f"{kind} {i}: m={g.m} bf={bf}", flush=True)
+            data[f"{kind}:{n}"] = {"graphs": n, "m": m_tot, "butterflies": bf_tot,
+                                   "sup_sha256": hs.hexdigest(), "phi_sha256": hp.hexdigest(),
+                                   "per_graph": per[:64],
+                                   "oracle_seconds": round(time.time() - t0, 1),
+                                   "oracle_threads": oracle.max_threads(),
+                                   "generator_version": synth.GENERATOR_VERSION}
+        else:
+            raise SystemExit(f"unknown workload {a}")
+        json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+        print("wrote", a, flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["uniform10k"])

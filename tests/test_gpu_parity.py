@@ -128,3 +128,24 @@ def test_batch_equals_plain():
     for g, s, p in zip(gs, sups, phis):
         osup, _, ophi = oracle_all(g)
         assert np.array_equal(s.cpu().numpy(), osup) and np.array_equal(p.cpu().numpy(), ophi)
+
+
+def test_batch_rejects_malformed_member():
+    gs = [synth.batch_graph(i) for i in range(3)]
+    dgs = [upload(g) for g in gs]
+    bad = gs[1].col.copy()
+    bad[0] = gs[1].n_lower  # out of range for its own graph, inside the next one's
+    dgs[1] = binding.DeviceGraph(gs[1].n_upper, gs[1].n_lower, torch.from_numpy(gs[1].row_ptr).cuda(),
+                                 torch.from_numpy(bad).cuda())
+    with pytest.raises(binding.BtError) as ei:
+        binding.bt_decompose_batch(dgs)
+    assert ei.value.status == binding.BT_EINVAL
+
+
+def test_batch_with_empty_members():
+    gs = [synth.from_edges(3, 3, []), synth.batch_graph(5), synth.from_edges(0, 0, []),
+          graphs.k2_1001(), synth.batch_graph(6)]
+    sups, phis, st = binding.bt_decompose_batch([upload(g) for g in gs], stats=True)
+    for g, s, p in zip(gs, sups, phis):
+        osup, _, ophi = oracle_all(g)
+        assert np.array_equal(s.cpu().numpy(), osup) and np.array_equal(p.cpu().numpy(), ophi)
