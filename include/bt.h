@@ -157,6 +157,43 @@ bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
 bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const *sup_out,
                              int64_t *const *phi_out, bt_stats *stats, hipStream_t stream);
 
+/*
+ * Serving engine with continuous batching (for request streams).
+ *
+ * bt_engine_create: `slots` worker slots (0: 2), each with its own HIP
+ *   stream and workspace; `hbm_budget` bytes of device memory for requests
+ *   in flight (0: half of the free memory); at most `max_batch` requests
+ *   per batch (0: 1024).
+ * bt_engine_submit: queue one request.  Validates the graph and estimates
+ *   its device memory on the device (index and peel state bounded through
+ *   the wedge bound of Lemma 6, sum over edges of min(d(u), d(v)), plus
+ *   per-edge arrays).  BT_EINVAL for a malformed graph, BT_EBUSY if the
+ *   estimate exceeds the whole budget.  Graph and outputs are caller-owned
+ *   DEVICE memory that must stay valid until the request completes;
+ *   sup_out may be NULL.  Results equal bt_decompose on the same graph.
+ * A free slot admits, in arrival order, every queued request that fits
+ *   the budget left by the other slots and decomposes them as one batch
+ *   (bt_decompose_batch semantics); requests that arrive meanwhile go to
+ *   the next free slot, so batches overlap on the device.
+ * bt_engine_poll: moves up to `cap` completed (id, status) pairs to the
+ *   caller's host arrays; *n_done receives how many.
+ * bt_engine_drain: blocks until every submitted request has completed.
+ * bt_engine_destroy: drains, stops the workers and frees the engine.
+ */
+typedef struct bt_engine bt_engine;
+
+bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
+                           bt_engine **out);
+bt_status bt_engine_submit(bt_engine *engine, const bt_csr *g, int64_t *sup_out,
+                           int64_t *phi_out, uint64_t id);
+bt_status bt_engine_poll(bt_engine *engine, uint64_t *ids, int32_t *status, int32_t cap,
+                         int32_t *n_done);
+bt_status bt_engine_drain(bt_engine *engine);
+/* Batches run, requests admitted and requests waiting (host pointers, nullable). */
+bt_status bt_engine_stats(bt_engine *engine, int64_t *batches, int64_t *admitted,
+                          int64_t *queued);
+void bt_engine_destroy(bt_engine *engine);
+
 /* Free the cached device workspace (it regrows on the next call). */
 void bt_release_workspace(void);
 

@@ -214,3 +214,90 @@ def bt_release_workspace():
 
 def bt_version() -> str:
     return load().bt_version().decode()
+
+
+# --- serving engine ----------------------------------------------------------
+
+EXPORTED += ["bt_engine_create", "bt_engine_submit", "bt_engine_poll", "bt_engine_drain",
+             "bt_engine_stats", "bt_engine_destroy"]
+
+
+def _engine_lib():
+    L = load()
+    if not getattr(L, "_engine_ready", False):
+        p, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        L.bt_engine_create.argtypes = [i64, i32, i32, ctypes.POINTER(p)]
+        L.bt_engine_submit.argtypes = [p, ctypes.POINTER(bt_csr), p, p, u64]
+        L.bt_engine_poll.argtypes = [p, ctypes.POINTER(u64), ctypes.POINTER(i32), i32,
+                                     ctypes.POINTER(i32)]
+        L.bt_engine_drain.argtypes = [p]
+        L.bt_engine_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
+        L.bt_engine_destroy.argtypes = [p]
+        L.bt_engine_destroy.restype = None
+        for n in ("bt_engine_create", "bt_engine_submit", "bt_engine_poll", "bt_engine_drain",
+                  "bt_engine_stats"):
+            getattr(L, n).restype = ctypes.c_int
+        L._engine_ready = True
+    return L
+
+
+class BtEngine:
+    """bt_engine_* handle.  Keeps each request's graph and outputs alive until
+    it completes; results are device tensors."""
+
+    def __init__(self, hbm_budget: int = 0, slots: int = 2, max_batch: int = 1024):
+        L = _engine_lib()
+        self._h = ctypes.c_void_p(0)
+        _check(L.bt_engine_create(int(hbm_budget), int(slots), int(max_batch),
+                                  ctypes.byref(self._h)))
+        self._live = {}
+        self.results = {}
+
+    def bt_engine_submit(self, g: DeviceGraph, req_id: int, want_sup: bool = False):
+        L = _engine_lib()
+        dev = g.col.device
+        phi = torch.empty(g.m, dtype=torch.int64, device=dev)
+        sup = torch.empty(g.m, dtype=torch.int64, device=dev) if want_sup else None
+        c = g.csr()
+        # the engine reads the graph on its own streams: finish pending uploads
+        torch.cuda.current_stream().synchronize()
+        rc = L.bt_engine_submit(self._h, ctypes.byref(c), _ptr(sup), _ptr(phi),
+                                ctypes.c_uint64(req_id))
+        _check(rc)
+        self._live[req_id] = (g, sup, phi)
+
+    def bt_engine_poll(self, cap: int = 4096):
+        """Completed (id, status) pairs; their (sup, phi) move to self.results."""
+        L = _engine_lib()
+        ids = (ctypes.c_uint64 * cap)()
+        st = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32(0)
+        _check(L.bt_engine_poll(self._h, ids, st, cap, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            rid, s = int(ids[i]), int(st[i])
+            g, sup, phi = self._live.pop(rid)
+            self.results[rid] = (s, sup, phi)
+            out.append((rid, s))
+        return out
+
+    def bt_engine_drain(self):
+        _check(_engine_lib().bt_engine_drain(self._h))
+
+    def bt_engine_stats(self):
+        b, a, q = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_engine_lib().bt_engine_stats(self._h, ctypes.byref(b), ctypes.byref(a),
+                                             ctypes.byref(q)))
+        return {"batches": b.value, "admitted": a.value, "queued": q.value}
+
+    def bt_engine_destroy(self):
+        if self._h:
+            _engine_lib().bt_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.bt_engine_destroy()
+        except Exception:
+            pass

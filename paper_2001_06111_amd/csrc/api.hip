@@ -35,6 +35,8 @@ template <class F> bt_status guard(F &&f) {
     }
 }
 
+}  // namespace
+
 void check_graph(const bt_csr *g) {
     if (!g) throw Error{BT_EINVAL, "graph descriptor is NULL"};
     if (g->n_upper < 0 || g->n_lower < 0 || g->m < 0)
@@ -45,6 +47,8 @@ void check_graph(const bt_csr *g) {
     if (!g->row_ptr) throw Error{BT_EINVAL, "row_ptr is NULL"};
     if (g->m > 0 && !g->col) throw Error{BT_EINVAL, "col is NULL"};
 }
+
+namespace {
 
 struct Events {
     bool on = false;
@@ -114,7 +118,7 @@ void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
     BT_HIP(hipMemsetAsync(ix.cursor, 0, sizeof(uint64_t) * 2, s));
     build_index(r, t, ix, ws, s);
     if (ev) ev->mark(2);
-    int64_t *hs = host_scalars(4);
+    int64_t *hs = ws.host(4);
     BT_HIP(hipMemcpyAsync(hs, ix.cursor, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
     const uint64_t c = (uint64_t)hs[0];
@@ -122,6 +126,9 @@ void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
     ix.n_w = (int64_t)(c & 0xffffffffu);
 }
 
+}  // namespace
+
+namespace {
 void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const PeelCounters &pc,
                 int64_t m, int64_t butterflies, Events &ev) {
     std::memset(stats, 0, sizeof *stats);
@@ -141,6 +148,8 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->ms_peel = ev.ms(3, 4);
 }
 
+}  // namespace
+
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
                     Workspace &ws, hipStream_t stream) {
     Events ev(stats != nullptr, stream);
@@ -152,11 +161,13 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
     PeelCounters pc;
     peel(r, ix, sup_out, phi_out, pc, ws, stream);
     ev.mark(4);
-    int64_t *hs = host_scalars(2);
+    int64_t *hs = ws.host(2);
     BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     BT_HIP(hipStreamSynchronize(stream));
     if (stats) fill_stats(stats, r, ix, pc, g.m, hs[0], ev);
 }
+
+namespace {
 
 // ---- batches: many graphs decomposed as one disjoint union --------------
 // A butterfly never spans two connected components, so the supports and
@@ -300,6 +311,8 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
 // inside the index limits; an oversized union is split in halves.
 constexpr int64_t kBatchEdges = int64_t(1) << 25;
 
+}  // namespace
+
 void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
                           hipStream_t s) {
@@ -313,8 +326,6 @@ void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
         a = b;
     }
 }
-
-}  // namespace
 
 }  // namespace bt
 
@@ -357,7 +368,7 @@ bt_status bt_support(const bt_csr *g, int64_t *sup_out, int64_t *butterflies_out
         BT_HIP(hipMemsetAsync(bf, 0, sizeof(int64_t) * 2, stream));
         count_support(r, t, supl, bf, stream);
         supl_to_sup(supl, sup_out, g->m, stream);
-        int64_t *hs = host_scalars(2);
+        int64_t *hs = ws.host(2);
         BT_HIP(hipMemcpyAsync(hs, bf, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         BT_HIP(hipStreamSynchronize(stream));
         if (butterflies_out) *butterflies_out = hs[0];
@@ -375,7 +386,7 @@ bt_status bt_index_build(const bt_csr *g, bt_index **out, hipStream_t stream) {
         try {
             RankCSR r;
             build_all(*g, r, h->ix, true, &h->owned, ws, stream, nullptr);
-            int64_t *hs = host_scalars(2);
+            int64_t *hs = ws.host(2);
             BT_HIP(hipMemcpyAsync(hs, h->ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost,
                                   stream));
             BT_HIP(hipStreamSynchronize(stream));

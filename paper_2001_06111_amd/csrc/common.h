@@ -45,6 +45,9 @@ inline int bits_for(uint64_t v) {  // bits needed to store values in [0, v]
 
 // A named set of device buffers that grow on demand and are kept between
 // calls.  Buffers are 256-byte aligned.  Not thread-safe: owners lock.
+// Also owns pinned host scratch for small device-to-host reads and the
+// peel's captured round graphs, so independent workspaces can serve
+// concurrent calls on different streams.
 class Workspace {
 public:
     ~Workspace();
@@ -52,8 +55,17 @@ public:
     template <typename T> T *get(const char *name, int64_t count) {
         return static_cast<T *>(get(name, (size_t)(count > 0 ? count : 1) * sizeof(T)));
     }
+    int64_t *host(int n);  // pinned, at least n int64; valid until a larger request
     void release();
     size_t bytes() const;
+
+    struct GraphEntry {
+        std::vector<unsigned char> key;
+        int rounds;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    bool coop = true;  // peel with the cooperative persistent kernel
 
 private:
     struct Buf {
@@ -62,13 +74,13 @@ private:
         size_t cap = 0;
     };
     std::vector<Buf> bufs_;
+    int64_t *host_ = nullptr;
+    int host_cap_ = 0;
 };
 
 void *device_alloc(size_t bytes);  // throws BT_ENOMEM with the size
 void device_free(void *p);
 
-// Pinned host scratch for small device-to-host reads (grows, kept).
-int64_t *host_scalars(int n);
 
 // ------------------------------------------------------ wave primitives
 

@@ -1,0 +1,251 @@
+// engine.hip - serving with continuous batching.
+//
+// Requests (device CSRs with caller-owned outputs) are queued with a
+// device-memory estimate taken at submit time.  Each worker slot owns a HIP
+// stream and a workspace; when a slot is free it admits, in arrival order,
+// every queued request whose estimate still fits the engine's memory
+// budget (less what the other slots hold) and decomposes them together as
+// one disjoint union.  Requests that arrive while batches run are admitted
+// by the next free slot, so batches on different slots overlap on the GPU.
+// Each result equals the plain single-graph decomposition of the request.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "pipeline.h"
+
+namespace bt {
+namespace {
+
+struct Request {
+    bt_csr g;
+    int64_t *sup;
+    int64_t *phi;
+    uint64_t id;
+    int64_t bytes;
+};
+
+struct Done {
+    uint64_t id;
+    bt_status st;
+};
+
+}  // namespace
+}  // namespace bt
+
+using namespace bt;
+
+struct bt_engine {
+    int64_t budget = 0;
+    int32_t max_batch = 1024;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_idle;
+    std::deque<Request> queue;
+    std::vector<Done> done;
+    int64_t reserved = 0;  // estimates of the batches now running
+    int64_t running = 0;   // requests now running
+    bool stop = false;
+    std::vector<std::thread> workers;
+    // submit-time estimates run on their own stream and workspace
+    std::mutex est_mu;
+    Workspace est_ws;
+    hipStream_t est_stream = nullptr;
+    int device = 0;
+    int64_t batches = 0, admitted = 0;
+
+    void worker_loop(int slot);
+};
+
+void bt_engine::worker_loop(int slot) {
+    (void)hipSetDevice(device);
+    hipStream_t s = nullptr;
+    (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    Workspace ws;
+    ws.coop = false;  // slots overlap: the peel must not wait on co-resident blocks
+    (void)slot;
+    while (true) {
+        std::vector<Request> batch;
+        int64_t bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] {
+                if (stop) return true;
+                return !queue.empty() && reserved + queue.front().bytes <= budget;
+            });
+            if (stop) break;  // destroy drains the queue before it stops workers
+            // Admit in arrival order while the budget allows.
+            while (!queue.empty() && (int32_t)batch.size() < max_batch &&
+                   reserved + bytes + queue.front().bytes <= budget) {
+                bytes += queue.front().bytes;
+                batch.push_back(queue.front());
+                queue.pop_front();
+            }
+            reserved += bytes;
+            running += (int64_t)batch.size();
+            batches += 1;
+            admitted += (int64_t)batch.size();
+        }
+        std::vector<bt_csr> gs;
+        std::vector<int64_t *> sups, phis;
+        for (auto &r : batch) {
+            gs.push_back(r.g);
+            sups.push_back(r.sup);
+            phis.push_back(r.phi);
+        }
+        std::vector<Done> out;
+        try {
+            decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), nullptr,
+                                 ws, s);
+            for (auto &r : batch) out.push_back(Done{r.id, BT_OK});
+        } catch (const Error &) {
+            // Isolate the failure: run the requests of the batch one by one.
+            for (auto &r : batch) {
+                bt_status st = BT_OK;
+                try {
+                    decompose_batch_impl(&r.g, 1, &r.sup, &r.phi, nullptr, ws, s);
+                } catch (const Error &e) {
+                    st = e.status;
+                } catch (...) {
+                    st = BT_EDEVICE;
+                }
+                out.push_back(Done{r.id, st});
+            }
+        } catch (...) {
+            for (auto &r : batch) out.push_back(Done{r.id, BT_EDEVICE});
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            reserved -= bytes;
+            running -= (int64_t)batch.size();
+            for (auto &d : out) done.push_back(d);
+        }
+        cv_work.notify_all();
+        cv_idle.notify_all();
+    }
+    ws.release();
+    if (s) (void)hipStreamDestroy(s);
+}
+
+extern "C" {
+
+bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
+                           bt_engine **out) {
+    if (!out || slots < 0 || max_batch < 0) {
+        set_error("invalid engine arguments");
+        return BT_EINVAL;
+    }
+    *out = nullptr;
+    bt_engine *E = new bt_engine();
+    try {
+        BT_HIP(hipGetDevice(&E->device));
+        if (hbm_budget <= 0) {
+            size_t fr = 0, tot = 0;
+            BT_HIP(hipMemGetInfo(&fr, &tot));
+            hbm_budget = (int64_t)(fr / 2);
+        }
+        E->budget = hbm_budget;
+        E->max_batch = max_batch > 0 ? max_batch : 1024;
+        BT_HIP(hipStreamCreateWithFlags(&E->est_stream, hipStreamNonBlocking));
+        E->est_ws.coop = false;
+        const int n = slots > 0 ? slots : 2;
+        for (int i = 0; i < n; ++i) E->workers.emplace_back(&bt_engine::worker_loop, E, i);
+    } catch (const Error &e) {
+        set_error(e.msg);
+        delete E;
+        return e.status;
+    }
+    *out = E;
+    return BT_OK;
+}
+
+bt_status bt_engine_submit(bt_engine *E, const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
+                           uint64_t id) {
+    if (!E) {
+        set_error("engine is NULL");
+        return BT_EINVAL;
+    }
+    Request r{};
+    try {
+        check_graph(g);
+        if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
+        std::lock_guard<std::mutex> lk(E->est_mu);
+        r.bytes = footprint_bytes(*g, E->est_ws, E->est_stream);
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.status;
+    }
+    if (r.bytes > E->budget) {
+        set_error("request needs about " + std::to_string(r.bytes) +
+                  " bytes, more than the engine budget");
+        return BT_EBUSY;
+    }
+    r.g = *g;
+    r.sup = sup_out;
+    r.phi = phi_out;
+    r.id = id;
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        E->queue.push_back(r);
+    }
+    E->cv_work.notify_one();
+    return BT_OK;
+}
+
+bt_status bt_engine_poll(bt_engine *E, uint64_t *ids, int32_t *status, int32_t cap,
+                         int32_t *n_done) {
+    if (!E || !n_done || (cap > 0 && (!ids || !status))) {
+        set_error("invalid poll arguments");
+        return BT_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(E->mu);
+    const int32_t n = std::min<int32_t>(cap, (int32_t)E->done.size());
+    for (int32_t i = 0; i < n; ++i) {
+        ids[i] = E->done[i].id;
+        status[i] = E->done[i].st;
+    }
+    E->done.erase(E->done.begin(), E->done.begin() + n);
+    *n_done = n;
+    return BT_OK;
+}
+
+bt_status bt_engine_drain(bt_engine *E) {
+    if (!E) {
+        set_error("engine is NULL");
+        return BT_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(E->mu);
+    E->cv_idle.wait(lk, [&] { return E->queue.empty() && E->running == 0; });
+    return BT_OK;
+}
+
+bt_status bt_engine_stats(bt_engine *E, int64_t *batches, int64_t *admitted, int64_t *queued) {
+    if (!E) {
+        set_error("engine is NULL");
+        return BT_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(E->mu);
+    if (batches) *batches = E->batches;
+    if (admitted) *admitted = E->admitted;
+    if (queued) *queued = (int64_t)E->queue.size();
+    return BT_OK;
+}
+
+void bt_engine_destroy(bt_engine *E) {
+    if (!E) return;
+    bt_engine_drain(E);
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        E->stop = true;
+    }
+    E->cv_work.notify_all();
+    for (auto &t : E->workers) t.join();
+    E->est_ws.release();
+    if (E->est_stream) (void)hipStreamDestroy(E->est_stream);
+    delete E;
+}
+
+}  // extern "C"

@@ -156,7 +156,7 @@ void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
     r.n = (int32_t)n;
     r.m = m;
 
-    int64_t *hs = host_scalars(4);
+    int64_t *hs = ws.host(4);
     int32_t *flags = ws.get<int32_t>("prep_flags", 4);
     BT_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
     if (nu > 0) {
@@ -305,7 +305,7 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
                                                               r.n_lower, counts);
         BT_CHECK_LAUNCH();
     }
-    int64_t *hs = host_scalars(4);
+    int64_t *hs = ws.host(4);
     BT_HIP(hipMemcpyAsync(hs, counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     BT_HIP(hipMemcpyAsync(hs + 2, r.wpre + 2 * r.m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
@@ -323,6 +323,68 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
                                                              r.n_lower, t.hash, t.dense, cur);
         BT_CHECK_LAUNCH();
     }
+}
+
+}  // namespace bt
+
+// ------------------------------------------------------ footprint
+
+namespace bt {
+
+namespace {
+
+// sum over edges of min(d(u), d(v)): one wave per upper row.
+__global__ __launch_bounds__(kBlock) void k_min_degree_sum(const int64_t *row_ptr,
+                                                           const int32_t *col,
+                                                           const int32_t *deg_lower,
+                                                           int32_t n_upper,
+                                                           unsigned long long *out) {
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    unsigned long long acc = 0;
+    for (int64_t i = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < n_upper;
+         i += waves) {
+        const int64_t a = row_ptr[i], b = row_ptr[i + 1];
+        const int32_t du = (int32_t)(b - a);
+        for (int64_t k = a + lane_id(); k < b; k += kWave) {
+            const int32_t dl = deg_lower[col[k]];
+            acc += (unsigned long long)(du < dl ? du : dl);
+        }
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+
+}  // namespace
+
+int64_t footprint_bytes(const bt_csr &g, Workspace &ws, hipStream_t s) {
+    const int32_t nu = g.n_upper, nl = g.n_lower;
+    const int64_t m = g.m;
+    int32_t *flags = ws.get<int32_t>("fp_flags", 4);
+    int32_t *deg = ws.get<int32_t>("fp_deg", nl);
+    unsigned long long *sum = ws.get<unsigned long long>("fp_sum", 1);
+    BT_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
+    if (nu > 0) {
+        k_validate<<<grid_for((int64_t)nu * kWave, kBlock, 16384), kBlock, 0, s>>>(
+            g.row_ptr, g.col, nu, nl, m, flags);
+        BT_CHECK_LAUNCH();
+    }
+    int64_t *hs = ws.host(4);
+    BT_HIP(hipMemcpyAsync(hs, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipStreamSynchronize(s));
+    if (*(int32_t *)hs != 0 || (nu == 0 && m != 0)) throw Error{BT_EINVAL, "malformed graph"};
+    BT_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (nl > 0 ? nl : 1), s));
+    BT_HIP(hipMemsetAsync(sum, 0, sizeof(unsigned long long), s));
+    if (m > 0) {
+        k_lower_degree<<<grid_for(m, 256, 16384), 256, 0, s>>>(g.col, m, deg);
+        BT_CHECK_LAUNCH();
+        k_min_degree_sum<<<grid_for((int64_t)nu * kWave, kBlock, 16384), kBlock, 0, s>>>(
+            g.row_ptr, g.col, deg, nu, sum);
+        BT_CHECK_LAUNCH();
+    }
+    BT_HIP(hipMemcpyAsync(hs, sum, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipStreamSynchronize(s));
+    const int64_t wbound = hs[0];  // priority-obeyed wedges <= this (Lemma 6)
+    return 60 * wbound + 250 * m + 40 * ((int64_t)nu + nl) + (int64_t(1) << 20);
 }
 
 }  // namespace bt

@@ -440,7 +440,7 @@ __device__ bool grid_sync(GridBar *B, u64 &gen_local) {
             int64_t spins = 0;
             while (ld(&B->gen.v) == gen_local) {
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > (int64_t(1) << 23) || ld(&B->fail)) {
+                if (++spins > (int64_t(1) << 28) || ld(&B->fail)) {
                     __hip_atomic_store(&B->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
@@ -586,21 +586,12 @@ void launch_round(const PeelArgs &P, int p, hipStream_t s) {
     k_phase_b<<<grid_b(), kBlock, 0, s>>>(P, p);
 }
 
-// Captured chunks of `rounds` rounds, cached by argument bytes.
-struct GraphEntry {
-    std::vector<unsigned char> key;
-    int rounds;
-    hipGraphExec_t exec;
-};
-std::vector<GraphEntry> &graph_cache() {
-    static std::vector<GraphEntry> *c = new std::vector<GraphEntry>();
-    return *c;
-}
-
-hipGraphExec_t chunk_graph(const PeelArgs &P, int rounds, hipStream_t s) {
+// Captured chunks of `rounds` rounds, cached in the workspace by argument
+// bytes.
+hipGraphExec_t chunk_graph(const PeelArgs &P, int rounds, Workspace &ws) {
     std::vector<unsigned char> key(sizeof(PeelArgs));
     std::memcpy(key.data(), &P, sizeof(PeelArgs));
-    auto &cache = graph_cache();
+    auto &cache = ws.graphs;
     for (auto &g : cache)
         if (g.rounds == rounds && g.key == key) return g.exec;
     if (cache.size() >= 16) {
@@ -617,8 +608,7 @@ hipGraphExec_t chunk_graph(const PeelArgs &P, int rounds, hipStream_t s) {
     BT_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
     (void)hipStreamDestroy(cs);
-    cache.push_back(GraphEntry{key, rounds, ex});
-    (void)s;
+    cache.push_back(Workspace::GraphEntry{key, rounds, ex});
     return ex;
 }
 
@@ -668,12 +658,12 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     init.gmin[0] = init.gmin[1] = INT_MAX;
     BT_HIP(hipMemcpyAsync(P.ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
 
-    PeelCtl *hc = reinterpret_cast<PeelCtl *>(host_scalars((int)(sizeof(PeelCtl) / 8 + 40)));
+    PeelCtl *hc = reinterpret_cast<PeelCtl *>(ws.host((int)(sizeof(PeelCtl) / 8 + 40)));
     u64 *hr = reinterpret_cast<u64 *>(hc + 1);
     // BT_PEEL_MODE=graph replays captured two-kernel rounds instead of the
     // persistent kernel; BT_PEEL_GRAPH=0 launches those rounds directly.
     const char *mv = std::getenv("BT_PEEL_MODE");
-    const bool persistent = !(mv && std::strcmp(mv, "graph") == 0);
+    const bool persistent = ws.coop && !(mv && std::strcmp(mv, "graph") == 0);
     const char *gv = std::getenv("BT_PEEL_GRAPH");
     const bool use_graph = !(gv && std::atoi(gv) == 0);
     GridBar *bar = ws.get<GridBar>("peel_bar", 1);
@@ -754,7 +744,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
                                               dim3(kPBlock), args, 0, s));
         } else if (use_graph) {
-            BT_HIP(hipGraphLaunch(chunk_graph(P, chunk, s), s));
+            BT_HIP(hipGraphLaunch(chunk_graph(P, chunk, ws), s));
         } else {
             for (int rr = 0; rr < chunk; ++rr) launch_round(P, rr & 1, s);
             BT_CHECK_LAUNCH();

@@ -85,6 +85,19 @@ struct PeelCounters {
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s);
 
+// Whole decompositions (api.hip): one graph, or many as disjoint unions.
+void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
+                    Workspace &ws, hipStream_t stream);
+void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
+                          int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
+                          hipStream_t s);
+void check_graph(const bt_csr *g);
+
+// Device-memory estimate of decomposing g (validates g; BT_EINVAL if
+// malformed): index and peel state bounded through the wedge bound
+// sum over edges of min(d(u), d(v)) (Lemma 6), plus per-edge arrays.
+int64_t footprint_bytes(const bt_csr &g, Workspace &ws, hipStream_t s);
+
 // supl low halves to int64 supports.
 void supl_to_sup(const uint64_t *supl, int64_t *sup, int64_t m, hipStream_t s);
 

@@ -1,5 +1,4 @@
 // prims.hip - device-wide scans, stable radix sort, fills, workspace.
-#include <mutex>
 
 #include "common.h"
 
@@ -60,8 +59,13 @@ void *Workspace::get(const char *name, size_t bytes) {
 }
 
 void Workspace::release() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
     for (auto &b : bufs_) device_free(b.ptr);
     bufs_.clear();
+    if (host_) (void)hipHostFree(host_);
+    host_ = nullptr;
+    host_cap_ = 0;
 }
 
 size_t Workspace::bytes() const {
@@ -70,18 +74,16 @@ size_t Workspace::bytes() const {
     return t;
 }
 
-int64_t *host_scalars(int n) {
-    static int64_t *buf = nullptr;
-    static int cap = 0;
-    static std::mutex mu;
-    std::lock_guard<std::mutex> lk(mu);
-    if (n > cap) {
-        if (buf) (void)hipHostFree(buf);
-        buf = nullptr;
-        BT_HIP(hipHostMalloc((void **)&buf, sizeof(int64_t) * n, hipHostMallocDefault));
-        cap = n;
+int64_t *Workspace::host(int n) {
+    if (n > host_cap_) {
+        if (host_) (void)hipHostFree(host_);
+        host_ = nullptr;
+        host_cap_ = 0;
+        const int cap = n > 4096 ? n : 4096;
+        BT_HIP(hipHostMalloc((void **)&host_, sizeof(int64_t) * cap, hipHostMallocDefault));
+        host_cap_ = cap;
     }
-    return buf;
+    return host_;
 }
 
 int grid_for(int64_t n, int block, int max_blocks) {

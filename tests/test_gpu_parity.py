@@ -149,3 +149,55 @@ def test_batch_with_empty_members():
     for g, s, p in zip(gs, sups, phis):
         osup, _, ophi = oracle_all(g)
         assert np.array_equal(s.cpu().numpy(), osup) and np.array_equal(p.cpu().numpy(), ophi)
+
+
+# --- serving engine -----------------------------------------------------------
+
+def _run_engine(gs, slots=2, budget=0, stagger=0.0):
+    import time
+    eng = binding.BtEngine(hbm_budget=budget, slots=slots)
+    dgs = [upload(g) for g in gs]
+    for i, d in enumerate(dgs):
+        eng.bt_engine_submit(d, i, want_sup=True)
+        if stagger:
+            time.sleep(stagger)
+    eng.bt_engine_drain()
+    done = eng.bt_engine_poll()
+    stats = eng.bt_engine_stats()
+    eng.bt_engine_destroy()
+    torch.cuda.synchronize()
+    return eng.results, done, stats
+
+
+def test_engine_alone_equals_mix():
+    """Each request's result is the same alone and in the mix (and equals the oracle)."""
+    gs = [synth.batch_graph(i) for i in range(24)] + [synth.scaled_chunglu(50_000, seed=4)]
+    mix, done, stats = _run_engine(gs, slots=2, stagger=0.002)
+    assert sorted(i for i, _ in done) == list(range(len(gs)))
+    assert stats["admitted"] == len(gs)
+    for i, g in enumerate(gs):
+        s, sup, phi = mix[i]
+        assert s == binding.BT_OK
+        alone, _, _ = _run_engine([g], slots=1)
+        assert torch.equal(alone[0][2], phi) and torch.equal(alone[0][1], sup)
+    for i in (0, 7, len(gs) - 1):
+        osup, _, ophi = oracle_all(gs[i])
+        assert np.array_equal(mix[i][1].cpu().numpy(), osup)
+        assert np.array_equal(mix[i][2].cpu().numpy(), ophi)
+
+
+def test_engine_rejects_and_isolates():
+    eng = binding.BtEngine(hbm_budget=1 << 20, slots=1)
+    g = synth.scaled_chunglu(200_000, seed=2)
+    with pytest.raises(binding.BtError) as ei:  # larger than the whole budget
+        eng.bt_engine_submit(upload(g), 1)
+    assert ei.value.status == binding.BT_EBUSY
+    bad = synth.uniform(10, 10, 30, 1)
+    col = bad.col.copy()
+    col[2] = 99
+    d = binding.DeviceGraph(bad.n_upper, bad.n_lower, torch.from_numpy(bad.row_ptr).cuda(),
+                            torch.from_numpy(col).cuda())
+    with pytest.raises(binding.BtError) as ei:
+        eng.bt_engine_submit(d, 2)
+    assert ei.value.status == binding.BT_EINVAL
+    eng.bt_engine_destroy()
