@@ -25,7 +25,7 @@ def phi_digest(phi) -> str:
     return hashlib.sha256(phi.astype("<i8").tobytes()).hexdigest()
 
 
-def cpu_baseline(g, frac: float, seed: int = 1):
+def cpu_baseline(g, frac: float, seed: int = 2027):
     """The oracle, untuned, on a vertex-sampled induced subgraph (host cores)."""
     import oracle
     from paper_2001_06111_amd import synth
@@ -43,13 +43,20 @@ def cpu_baseline(g, frac: float, seed: int = 1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-frac", type=float, default=0.3)
+    ap.add_argument("--cpu-frac", type=float, default=0.5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="chunglu5m", choices=["chunglu5m", "uniform10k", "hub20m"])
-    ap.add_argument("--batch", type=int, default=512,
+    ap.add_argument("--batch", type=int, default=256,
                     help="graphs of the many-small-graphs pool for the batched-vs-plain line (0: skip)")
+    ap.add_argument("--serve", type=float, default=1.0,
+                    help="seconds of Poisson arrivals for the served-vs-plain-FIFO line (0: skip)")
+    ap.add_argument("--serve-pool", type=int, default=512,
+                    help="small graphs in the request pool (of the 4096)")
+    ap.add_argument("--serve-big", type=int, default=4, help="2M-edge graphs in the request pool")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a 256 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -69,6 +76,12 @@ def main():
     sup = torch.empty(g.m, dtype=torch.int64, device="cuda:0")
     stream = torch.cuda.current_stream()
 
+    if args.calib:
+        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for i in range(args.warmup):
         binding.bt_decompose(dg, stats=True, out_phi=phi, out_sup=sup)
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
@@ -101,10 +114,13 @@ def main():
     check = "no-oracle-digest" if want is None else ("match" if want == digest else "MISMATCH")
 
     st = stats[-1]
-    # Dominant kernel: the wedge sweep (count + emit) of the index build.
-    wedge_ms = st["ms_count"]
-    alg_bytes = wedge_bytes(st, g.m)
-    achieved = alg_bytes / (wedge_ms / 1e3) / 1e9 if wedge_ms > 0 else 0.0
+    # Dominant kernel: the peel (over 95% of a step).  Its device time is
+    # taken by the library with HIP events around each launch on this stream.
+    peel_s = st["ms_peel_kernel"] / 1e3
+    alg_bytes = peel_bytes(st, g.m)
+    achieved = alg_bytes / peel_s / 1e9 if peel_s > 0 else 0.0
+    launches = max(1, st["peel_launches"])
+    traffic = measured_traffic(launches)
     out = {
         "metric": "edges decomposed/s (bit-exact phi_e), batched vs plain; p50/p99 latency",
         "value": g.m / (ms / 1000.0),
@@ -129,12 +145,16 @@ def main():
         "counters": {k: st[k] for k in ("butterflies", "wedges_po", "blooms", "bloom_wedges",
                                         "levels", "rounds", "max_phi", "support_updates",
                                         "bloom_visits", "index_bytes")},
-        "roofline": {"kernel": "wedge sweep (count + index emission)", "bound": "hbm",
+        "roofline": {"kernel": "k_peel_persistent (bloom peel, all rounds)", "bound": "hbm",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes / launches,
+                     "avg_launch_ms": st["ms_peel_kernel"] / launches, "launches": launches},
     }
     if args.batch > 0:
         out["batched"] = batch_compare(args.batch)
+    if args.serve > 0:
+        out["served"] = serve_compare(args.serve, args.serve_pool, args.serve_big)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_frac)
@@ -169,18 +189,120 @@ def batch_compare(n):
             "batched_rounds": st["rounds"]}
 
 
-def wedge_bytes(st, m):
-    """Algorithmic HBM bytes of the two wedge sweeps.
+def serve_compare(seconds, n_small, n_big, rate=200.0):
+    """p50/p99 latency and graphs/s: the serving engine vs a plain FIFO loop.
 
-    Per priority-obeyed wedge, each sweep reads the end vertex (4 B); the
-    emit sweep also reads the (y, z) edge id (4 B).  Per bloom wedge: the
-    wedge record (3 x 4 B) and one 8-byte atomic on the (y, z) edge word
-    (read + write).  Per edge: the per-(x, y) support/link word (8 B read +
-    write) once.
+    Poisson arrivals at `rate`/s for `seconds`; 95% of requests are graphs of
+    the small-graph pool, 5% are 2M-edge graphs (indices drawn from pools of
+    n_small and n_big graphs).  Latency = completion - arrival.
     """
-    w = st["wedges_po"]
-    nw = st["bloom_wedges"]
-    return 2 * 4 * w + 4 * w + nw * (12 + 16) + 16 * m
+    import threading
+    import numpy as np
+    import torch
+    from paper_2001_06111_amd import binding, synth
+    reqs = synth.serving_arrivals(rate=rate, duration=seconds, n_small=n_small, n_big=n_big)
+    small = {i: binding.DeviceGraph.upload(synth.batch_graph(i), "cuda:0")
+             for i in sorted({k for _, kind, k in reqs if kind == "small"})}
+    big = {j: binding.DeviceGraph.upload(synth.big_serving_graph(j), "cuda:0")
+           for j in sorted({k for _, kind, k in reqs if kind == "big"})}
+    graph = [small[k] if kind == "small" else big[k] for _, kind, k in reqs]
+    arrive = np.array([t for t, _, _ in reqs])
+    # warm both paths
+    binding.bt_decompose(graph[0])
+    torch.cuda.synchronize()
+
+    # plain FIFO: one request at a time, in arrival order
+    done_plain = np.zeros(len(reqs))
+    t0 = time.perf_counter()
+    for i, g in enumerate(graph):
+        now = time.perf_counter() - t0
+        if now < arrive[i]:
+            time.sleep(arrive[i] - now)
+        binding.bt_decompose(g, want_sup=False)
+        torch.cuda.synchronize()
+        done_plain[i] = time.perf_counter() - t0
+    span_plain = done_plain.max()
+    lat_plain = done_plain - arrive
+
+    # served: submit at arrival times, poll completions
+    eng = binding.BtEngine(slots=2)
+    done_srv = np.zeros(len(reqs))
+    t0 = time.perf_counter()
+    finished = threading.Event()
+
+    def poller():
+        got = 0
+        while got < len(reqs):
+            for rid, st in eng.bt_engine_poll():
+                done_srv[rid] = time.perf_counter() - t0
+                got += 1
+            time.sleep(0.0005)
+        finished.set()
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    for i, g in enumerate(graph):
+        now = time.perf_counter() - t0
+        if now < arrive[i]:
+            time.sleep(arrive[i] - now)
+        eng.bt_engine_submit(g, i)
+    finished.wait()
+    est = eng.bt_engine_stats()
+    eng.bt_engine_destroy()
+    span_srv = done_srv.max()
+    lat_srv = done_srv - arrive
+    same = True
+    for i in range(0, len(reqs), max(1, len(reqs) // 32)):
+        _, phi, _ = binding.bt_decompose(graph[i], want_sup=False)
+        same &= bool(torch.equal(phi, eng.results[i][2]))
+    print(f"[bench] serve {len(reqs)} reqs: plain p99 {np.percentile(lat_plain, 99):.3f}s "
+          f"served p99 {np.percentile(lat_srv, 99):.3f}s", file=sys.stderr, flush=True)
+    return {"workload": f"Poisson {rate:g}/s for {seconds:g}s: 95% small-pool graphs (of {n_small}), "
+                        f"5% 2M-edge graphs (of {n_big})",
+            "requests": len(reqs), "big_requests": sum(1 for _, k, _ in reqs if k == "big"),
+            "served_p50_s": float(np.percentile(lat_srv, 50)),
+            "served_p99_s": float(np.percentile(lat_srv, 99)),
+            "plain_p50_s": float(np.percentile(lat_plain, 50)),
+            "plain_p99_s": float(np.percentile(lat_plain, 99)),
+            "served_graphs_per_s": len(reqs) / span_srv, "plain_graphs_per_s": len(reqs) / span_plain,
+            "served_batches": est["batches"], "served_equals_plain": same}
+
+
+def peel_bytes(st, m):
+    """Algorithmic HBM bytes of the peel (what the method must move).
+
+    Per support decrement: a 4-byte read-modify-write (8 B).  Per link (each
+    of the 2 n_W edge-wedge links is walked once, when its edge is removed):
+    the 8-byte link, the wedge's alive word (RMW, 8 B), its two edge ids
+    (8 B) and the bloom's k and wedge range (12 B).  Per touched-bloom
+    visit: its C and k (8 B) and the 16-byte work item (written, read).
+    Per edge: one frontier item (16 B written and read) and its phi (4 B).
+    """
+    return (8 * st["support_updates"] + 36 * 2 * st["bloom_wedges"]
+            + 40 * st["bloom_visits"] + 36 * m)
+
+
+def measured_traffic(launches):
+    """HBM bytes per peel launch from the committed rocprofv3 counter summary.
+
+    profiles/peel_chunglu5m_traffic.md records FETCH_SIZE and WRITE_SIZE of
+    the peel kernel, scaled by what the counters read for a copy of known
+    size, together with the SHA-256 of the peel source they were taken on.
+    Returns None when the source has changed since (or no summary exists).
+    """
+    path = os.path.join(ROOT, "profiles", "peel_chunglu5m_traffic.md")
+    src = os.path.join(ROOT, "paper_2001_06111_amd", "csrc", "peel.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    want = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("peel_source_sha256") != want or "hbm_bytes_total" not in fields:
+        return None
+    return float(fields["hbm_bytes_total"]) / launches
 
 
 if __name__ == "__main__":

@@ -84,6 +84,8 @@ typedef struct bt_stats {
     float ms_count;           /* wedge counting and index emission */
     float ms_link;            /* edge-to-wedge links */
     float ms_peel;            /* peel */
+    float ms_peel_kernel;     /* device time of the peel kernels alone (HIP events) */
+    int32_t peel_launches;    /* peel kernel (or round-graph) launches */
 } bt_stats;
 
 /* Opaque device-resident BE-Index. */

@@ -35,7 +35,8 @@ class bt_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "butterflies", "wedges_po", "blooms", "bloom_wedges", "index_bytes", "levels",
         "rounds", "max_phi", "support_updates", "bloom_visits")] + [
-        (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel")]
+        (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel",
+                                      "ms_peel_kernel")] + [("peel_launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -262,10 +263,12 @@ class BtEngine:
         c = g.csr()
         # the engine reads the graph on its own streams: finish pending uploads
         torch.cuda.current_stream().synchronize()
+        self._live[req_id] = (g, sup, phi)  # before submit: it may complete at once
         rc = L.bt_engine_submit(self._h, ctypes.byref(c), _ptr(sup), _ptr(phi),
                                 ctypes.c_uint64(req_id))
+        if rc != BT_OK:
+            self._live.pop(req_id, None)
         _check(rc)
-        self._live[req_id] = (g, sup, phi)
 
     def bt_engine_poll(self, cap: int = 4096):
         """Completed (id, status) pairs; their (sup, phi) move to self.results."""

@@ -146,6 +146,8 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->ms_count = ev.ms(1, 2);
     stats->ms_link = ev.ms(2, 3);
     stats->ms_peel = ev.ms(3, 4);
+    stats->ms_peel_kernel = (float)pc.kernel_ms;
+    stats->peel_launches = (int32_t)pc.launches;
 }
 
 }  // namespace
@@ -241,6 +243,8 @@ void add_stats(bt_stats &t, const bt_stats &s) {
     t.ms_count += s.ms_count;
     t.ms_link += s.ms_link;
     t.ms_peel += s.ms_peel;
+    t.ms_peel_kernel += s.ms_peel_kernel;
+    t.peel_launches += s.peel_launches;
 }
 
 // Graphs [a, b) as one union; splits the range if the union is too large.

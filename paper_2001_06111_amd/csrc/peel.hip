@@ -679,6 +679,16 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         pblocks = std::max(1, std::min(pblocks, occ * cus));
     }
 
+    hipEvent_t ev0, ev1;  // around each peel launch: the kernel's device time
+    BT_HIP(hipEventCreate(&ev0));
+    BT_HIP(hipEventCreate(&ev1));
+    struct EvFree {
+        hipEvent_t a, b;
+        ~EvFree() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev_free{ev0, ev1};
     int64_t n_all = m;
     int cur = -1;  // -1: all edges, in id order
     int chunk = 4;
@@ -737,6 +747,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             BT_HIP(hipMemcpyAsync(P.ctl, &st, sizeof st, hipMemcpyHostToDevice, s));
             need_refill = false;
         }
+        BT_HIP(hipEventRecord(ev0, s));
         if (persistent) {
             int64_t max_rounds = 4 * m + 64;
             int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
@@ -749,8 +760,15 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             for (int rr = 0; rr < chunk; ++rr) launch_round(P, rr & 1, s);
             BT_CHECK_LAUNCH();
         }
+        BT_HIP(hipEventRecord(ev1, s));
         BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
         BT_HIP(hipStreamSynchronize(s));
+        {
+            float t = 0.f;
+            BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
+            pc.kernel_ms += t;
+            pc.launches += 1;
+        }
         if (persistent) {
             int32_t fail = 0;
             BT_HIP(hipMemcpy(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost));

@@ -81,6 +81,8 @@ void build_index(const RankCSR &r, const TaskLists &t, IndexArrays &ix, Workspac
 // supports, phi_out (int64) the bitruss numbers.
 struct PeelCounters {
     int64_t levels = 0, rounds = 0, max_phi = 0, updates = 0, bloom_visits = 0;
+    double kernel_ms = 0;  // HIP-event time of the peel kernel launches
+    int64_t launches = 0;
 };
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s);

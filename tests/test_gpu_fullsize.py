@@ -1,0 +1,59 @@
+"""Full-size parity: the 5M-edge Chung-Lu workload against the oracle.
+
+Bitruss numbers and supports are compared bit for bit through SHA-256
+digests of the oracle's outputs (tests/golden/digests.json, written by
+make_digests.py from the oracle); supports of sampled edges are also
+recounted one by one from the definition.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2001_06111_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "digests.json")))
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    g = synth.plain_chunglu_5m()
+    sup, phi, st = binding.bt_decompose(binding.DeviceGraph.upload(g), stats=True)
+    torch.cuda.synchronize()
+    return g, sup.cpu().numpy(), phi.cpu().numpy(), st
+
+
+def test_chunglu5m_digests(c1):
+    g, sup, phi, st = c1
+    want = GOLD[g.name]
+    assert want["generator_version"] == synth.GENERATOR_VERSION
+    assert st["butterflies"] == want["butterflies"]
+    assert sha(sup) == want["sup_sha256"]
+    assert sha(phi) == want["phi_sha256"]
+    assert st["levels"] == want["levels"] and st["max_phi"] == want["max_phi"]
+
+
+def test_chunglu5m_sampled_supports_and_invariants(c1):
+    g, sup, phi, st = c1
+    rng = np.random.default_rng(0)
+    pick = rng.choice(g.m, size=300, replace=False)
+    assert np.array_equal(oracle.edge_support(g.n_upper, g.n_lower, g.row_ptr, g.col, pick), sup[pick])
+    assert sup.sum() == 4 * st["butterflies"]
+    assert np.all(phi >= 0) and np.all(phi <= sup)
+
+
+def test_uniform10k_digests():
+    g = synth.plain_uniform_10k()
+    sup, phi, st = binding.bt_decompose(binding.DeviceGraph.upload(g), stats=True)
+    want = GOLD[g.name]
+    assert sha(sup.cpu().numpy()) == want["sup_sha256"] and sha(phi.cpu().numpy()) == want["phi_sha256"]
