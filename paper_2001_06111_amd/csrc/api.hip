@@ -94,14 +94,14 @@ void alloc_index(const RankCSR &r, IndexArrays &ix, bool owned, Workspace &ws,
     ix.wbl = (int32_t *)get("ix_wbl", sizeof(int32_t) * (ix.cap_w + 1));
     ix.supl = (uint64_t *)get("ix_supl", sizeof(uint64_t) * (m + 1));
     ix.link_off = (int64_t *)get("ix_link_off", sizeof(int64_t) * (m + 1));
-    ix.link = (uint2 *)get("ix_link", sizeof(uint2) * (2 * ix.cap_w + 1));
+    ix.link = (uint3 *)get("ix_link", sizeof(uint3) * (2 * ix.cap_w + 1));
     ix.cursor = (uint64_t *)get("ix_cursor", sizeof(uint64_t) * 2);
     ix.butterflies = (int64_t *)(ix.cursor + 1);
 }
 
 int64_t index_bytes(const IndexArrays &ix, int64_t m) {
     return (int64_t)(sizeof(uint32_t) + 2 * sizeof(int32_t)) * (ix.n_b + 1) +
-           (int64_t)(3 * sizeof(int32_t) + 2 * sizeof(uint2)) * ix.n_w +
+           (int64_t)(3 * sizeof(int32_t) + 2 * sizeof(uint3)) * ix.n_w +
            (int64_t)(sizeof(uint64_t) + sizeof(int64_t) + sizeof(int32_t) * 2) * m +
            (ix.n_w + 31) / 32 * 4;
 }
@@ -438,8 +438,8 @@ bt_status bt_index_export(const bt_index *idx, int64_t *bloom_woff, int32_t *wed
             BT_HIP(hipMemcpy(edge_link_off, ix.link_off, sizeof(int64_t) * (idx->m + 1),
                              hipMemcpyDeviceToHost));
         if (edge_link && ix.n_w) {
-            std::vector<uint2> t(2 * ix.n_w);
-            BT_HIP(hipMemcpy(t.data(), ix.link, sizeof(uint2) * t.size(),
+            std::vector<uint3> t(2 * ix.n_w);
+            BT_HIP(hipMemcpy(t.data(), ix.link, sizeof(uint3) * t.size(),
                              hipMemcpyDeviceToHost));
             for (size_t i = 0; i < t.size(); ++i) edge_link[i] = t[i].x;
         }

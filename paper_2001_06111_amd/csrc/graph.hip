@@ -384,7 +384,7 @@ int64_t footprint_bytes(const bt_csr &g, Workspace &ws, hipStream_t s) {
     BT_HIP(hipMemcpyAsync(hs, sum, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
     const int64_t wbound = hs[0];  // priority-obeyed wedges <= this (Lemma 6)
-    return 60 * wbound + 250 * m + 40 * ((int64_t)nu + nl) + (int64_t(1) << 20);
+    return 68 * wbound + 250 * m + 40 * ((int64_t)nu + nl) + (int64_t(1) << 20);
 }
 
 }  // namespace bt

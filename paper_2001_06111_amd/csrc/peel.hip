@@ -16,27 +16,31 @@
 // .)); subtracting unclamped and treating every support <= L as "at level
 // L" gives the same bitruss numbers, since max(M, max(M, a - d1) - d2) =
 // max(M, a - d1 - d2).  A decrement that takes a support from above L to at
-// most L puts the edge in the next frontier.  When a frontier is empty the
-// level rises to the minimum remaining support.
+// most L puts the edge in the next frontier (and fixes its phi = L: the
+// next round keeps the level).  When a frontier is empty the level rises to
+// the minimum remaining support.
 //
-// Device-driven rounds.  A round is two kernels that read their sizes from
-// a control block, so rounds are replayed from a captured HIP graph with
-// no host round trip:
-//   k_phase_a  normal round: the frontier edges' links, 64 per work item;
-//              gather round (first round of a level): the frontier becomes
-//              the active edges with support <= level, and the active set
-//              is compacted;
-//   k_phase_b  touched blooms, 64 wedges per work item; the last block to
-//              finish picks the next round: normal while a frontier exists,
-//              else a gather round at level + 1 (or, when a gather finds
-//              nothing, at the smallest support it saw).
-// One element per lane keeps every wave's chain of dependent atomics short.
+// Device-driven rounds.  The default is one persistent cooperative kernel
+// whose rounds are separated by grid barriers; the alternative is two
+// kernels per round replayed from a captured HIP graph (used where the
+// peel shares the device with other work).  Either way:
+//   phase A  normal round: the frontier edges' links, 64 per work item;
+//            gather round (first round of a level): the frontier becomes
+//            the active edges with support <= level, and the active set is
+//            compacted;
+//   phase B  touched blooms, 64 wedges per work item.
+// After each round one thread per block derives the next round from the
+// control block: normal while a frontier exists, else a gather at level + 1
+// (or, when a gather finds nothing, at the smallest support it saw).
+// Rounds are chains of dependent memory accesses, so the kernels keep those
+// chains short: one element per lane, independent accesses issued
+// together, small rounds spread over many CUs.
 // The active set holds the remaining edges with support below a threshold T
 // (a decrement that crosses T appends the edge).  When no active edge
 // remains the device raises `stall` and the host rebuilds the set with a
 // larger T from a histogram of the remaining supports.  Lists that one
 // round fills and the next consumes are double-buffered by round parity;
-// every counter is reset by a kernel that does not read it.
+// every counter is reset in a phase that does not read it.
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -77,9 +81,9 @@ struct PeelCtl {
     Counter na[2];      // active-set entries by buffer
     Counter updates;
     Counter bloom_visits;
-    // Round state, indexed by round parity.  Phase A of round r derives its
-    // own entry from round r - 1's final counters (every block computes the
-    // same values; block 0 stores them for phase B and for round r + 1).
+    // Round state, indexed by round parity.  Round r's entry is derived
+    // from round r - 1's final counters (every block computes the same
+    // values; block 0 stores them for round r + 1).
     int32_t mode[2];    // kNormal or kGather
     int32_t level[2];
     int32_t cur[2];     // active-set buffer in use
@@ -90,15 +94,21 @@ struct PeelCtl {
     int32_t pad;        // persistent kernel: parity of the next round
     u64 rounds, levels;
     u64 prof[6];        // persistent kernel, BT_PEEL_PROFILE=1: block-0 clock ticks
+    // BT_PEEL_PROFILE=1: frontier pushes by twin (phase A) and survivor
+    // (phase B) decrements, by list parity; rounds whose frontier came from
+    // twin decrements alone; log2 histograms of per-round work items.
+    Counter push_twin[2], push_surv[2];
+    u64 twin_only_rounds, twin_pushes, surv_pushes;
+    u64 hist_nf[32], hist_ntc[32];
 };
 
-struct FrontItem {
+struct alignas(16) FrontItem {
     int32_t e;
-    int32_t first;    // 1 for the edge's first chunk: assigns phi
+    int32_t rsv;      // unused (keeps items 16 bytes)
     uint32_t lo, hi;  // link positions of this chunk
 };
 
-struct BloomItem {
+struct alignas(16) BloomItem {
     int32_t b;
     int32_t nch;    // chunks of this bloom (the last one to finish finalizes)
     uint32_t lo, hi;  // wedge range of this chunk
@@ -117,11 +127,41 @@ struct PeelArgs {
     const int32_t *web;
     const int32_t *wbl;
     const int64_t *link_off;
-    const uint2 *link;  // {wedge, bloom}
+    const uint3 *link;  // {wedge, bloom, twin edge}
+    int32_t prof;       // count profile statistics
     FrontItem *front[2];
     BloomItem *tc[2];
     int32_t *act[2];
 };
+
+// Coherent access to state that blocks share within one launch.  The eight
+// XCDs keep separate L2 caches; device-scope loads and stores (relaxed
+// atomics) go to the point of coherence, so no round needs the L2 write-back
+// and invalidation that a device-scope fence costs, and the read-only index
+// stays cached in L2 across rounds.  Every access to mutable peel state
+// inside a launch goes through these.
+template <typename T> __device__ __forceinline__ T ld(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ void st(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// 16-byte work items move as two coherent 8-byte halves.
+template <typename Item> __device__ __forceinline__ void st_item(Item *p, const Item &v) {
+    static_assert(sizeof(Item) == 16, "work items are 16 bytes");
+    u64 h[2];
+    __builtin_memcpy(h, &v, 16);
+    st(reinterpret_cast<u64 *>(p), h[0]);
+    st(reinterpret_cast<u64 *>(p) + 1, h[1]);
+}
+template <typename Item> __device__ __forceinline__ Item ld_item(const Item *p) {
+    u64 h[2];
+    h[0] = ld(reinterpret_cast<const u64 *>(p));
+    h[1] = ld(reinterpret_cast<const u64 *>(p) + 1);
+    Item v;
+    __builtin_memcpy(&v, h, 16);
+    return v;
+}
 
 // Each lane asks for `cnt` consecutive slots of *counter; one atomic per
 // wave.  Must be called by all 64 lanes.
@@ -134,67 +174,104 @@ __device__ __forceinline__ u64 wave_alloc(uint32_t cnt, u64 *counter) {
     return base + inc - cnt;
 }
 
-// Append frontier work items (64-link chunks of edge e) where `take`.
-__device__ __forceinline__ void push_front(bool take, int32_t e, const PeelArgs &P, int q) {
-    uint32_t lo = 0, hi = 0, k = 0;
-    if (take) {
-        lo = (uint32_t)P.link_off[e];
-        hi = (uint32_t)P.link_off[(int64_t)e + 1];
-        k = hi - lo <= (uint32_t)kLinkChunk ? 1u : (hi - lo + kLinkChunk - 1) / kLinkChunk;
+// Slot requests against up to three counters (a null counter takes no
+// requests): each wave issues its atomics together and waits once.  Must be
+// called by all 64 lanes.
+__device__ __forceinline__ void wave_alloc3(uint32_t c0, u64 *k0, uint32_t c1, u64 *k1,
+                                            uint32_t c2, u64 *k2, u64 (&base)[3]) {
+    const uint32_t cnt[3] = {c0, c1, c2};
+    u64 *const ctr[3] = {k0, k1, k2};
+    uint32_t inc[3], tot[3];  // a wave's requests stay far below 2^32
+    u64 r[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        inc[k] = wave_inclusive_sum<uint32_t>(cnt[k]);
+        tot[k] = __shfl(inc[k], kWave - 1, kWave);
     }
-    const u64 base = wave_alloc(k, &P.ctl->nf[q].v);
+    if (lane_id() == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (tot[k]) r[k] = atomicAdd(ctr[k], (u64)tot[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) base[k] = __shfl(r[k], kWave - 1, kWave) + (inc[k] - cnt[k]);
+}
+
+// Frontier work items of an edge: its links in chunks of 64, at least one
+// chunk so that an edge without links still receives its bitruss number.
+__device__ __forceinline__ uint32_t link_chunks(uint32_t lo, uint32_t hi) {
+    return hi - lo <= (uint32_t)kLinkChunk ? 1u : (hi - lo + kLinkChunk - 1) / kLinkChunk;
+}
+
+// The pusher also records the edge's bitruss number: an edge is queued at
+// the level of the round that removes it (a queued frontier keeps the
+// level), and only a gather, which runs once the frontier is empty, reads
+// phi while the peel runs.
+__device__ __forceinline__ void put_front(const PeelArgs &P, int q, u64 base, int32_t e,
+                                          uint32_t lo, uint32_t hi, uint32_t k, int32_t level) {
+    if (k) st(&P.phi[e], level);
     for (uint32_t c = 0; c < k; ++c) {
         const uint32_t a = lo + c * kLinkChunk;
-        P.front[q][base + c] = FrontItem{e, c == 0 ? 1 : 0, a, min(a + (uint32_t)kLinkChunk, hi)};
+        st_item(&P.front[q][base + c], FrontItem{e, 0, a, min(a + (uint32_t)kLinkChunk, hi)});
     }
 }
 
-// Lower supports by d where `active`; both atomics issue before either
-// result is used.  Crossings of the level go to the next frontier, of the
-// threshold to the active set.
-__device__ __forceinline__ void dec_support2(bool act1, int32_t e1, bool act2, int32_t e2,
-                                             int32_t d, int32_t level, int32_t thresh,
-                                             const PeelArgs &P, int q, int cur) {
-    int32_t o1 = 0, o2 = 0;
-    if (act1) o1 = atomicSub(&P.sup[e1], d);
-    if (act2) o2 = atomicSub(&P.sup[e2], d);
-    const bool f1 = act1 && o1 > level && o1 - d <= level;
-    const bool f2 = act2 && o2 > level && o2 - d <= level;
-    const bool a1 = act1 && o1 >= thresh && o1 - d < thresh;
-    const bool a2 = act2 && o2 >= thresh && o2 - d < thresh;
-    push_front(f1, e1, P, q);
-    push_front(f2, e2, P, q);
-    const u64 slot = wave_alloc((a1 ? 1u : 0u) + (a2 ? 1u : 0u), &P.ctl->na[cur].v);
-    if (a1) P.act[cur][slot] = e1;
-    if (a2) P.act[cur][slot + (a1 ? 1 : 0)] = e2;
+enum : int { kSrcTwin = 0, kSrcSurvivor = 1 };
+
+// Profile statistics: frontier pushes by the decrement that caused them.
+__device__ __forceinline__ void count_push(const PeelArgs &P, int q, int src, uint32_t n) {
+    const u64 t = wave_sum<u64>((u64)n);
+    if (lane_id() == 0 && t)
+        atomicAdd(src == kSrcTwin ? &P.ctl->push_twin[q].v : &P.ctl->push_surv[q].v, t);
 }
 
-template <typename T> __device__ __forceinline__ T ld(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// Round parameters.  One thread per block reads them from the control block
+// after each barrier and hands them to the block through LDS, so the
+// control block sees one request per block, not one per wave.
 struct Round {
-    int32_t mode, level, cur;
-    u64 nf;  // frontier work items (normal rounds)
+    int32_t mode, level, cur, thresh;
+    u64 nf;   // frontier work items (normal rounds)
+    u64 na;   // active-set entries (gather rounds)
+    u64 ntc;  // bloom work items (phase B; read after the first barrier)
 };
 
-// Decide round r (parity p) from round r - 1's final counters.  Every
-// caller computes the same result; the lead stores it for phase B and for
-// round r + 1.  Returns false when the active set has run out (stall): the
-// host then rebuilds it, or finds that no edge remains.
-__device__ __forceinline__ bool decide_round(PeelCtl *C, int p, bool lead, Round &R) {
+// Round counters kept in the lead's registers while it runs.
+struct LeadStats {
+    u64 rounds, levels;
+    int32_t max_level;
+    __device__ void load(PeelCtl *C) {
+        rounds = ld(&C->rounds);
+        levels = ld(&C->levels);
+        max_level = ld(&C->max_level);
+    }
+    __device__ void store(PeelCtl *C) const {
+        st(&C->rounds, rounds);
+        st(&C->levels, levels);
+        st(&C->max_level, max_level);
+    }
+};
+
+// Decide round r (parity p) from round r - 1's final counters.  Every block
+// computes the same result; the lead stores it for round r + 1.  Returns
+// false when the active set has run out (stall): the host then rebuilds it,
+// or finds that no edge remains.
+__device__ __forceinline__ bool decide_round(PeelCtl *C, int p, bool lead, Round &R,
+                                             LeadStats &L, int prof) {
     const int q = p ^ 1;
     const int32_t pmode = ld(&C->mode[q]), plevel = ld(&C->level[q]), pcur = ld(&C->cur[q]);
     const int32_t pgmin = ld(&C->gmin[q]);
     const u64 nfp = ld(&C->nf[p].v);
+    const u64 na0 = ld(&C->na[0].v), na1 = ld(&C->na[1].v);
     R.cur = pmode == kGather ? pcur ^ 1 : pcur;
     R.nf = nfp;
+    R.thresh = ld(&C->thresh);
+    R.ntc = 0;
     if (nfp > 0) {
         R.mode = kNormal;
         R.level = plevel;
     } else if (pmode == kGather) {
         if (pgmin == INT_MAX) {  // no active edge left (or none at all)
-            if (lead) C->stall = 1;
+            if (lead) st(&C->stall, 1);
             return false;
         }
         R.mode = kGather;
@@ -203,14 +280,33 @@ __device__ __forceinline__ bool decide_round(PeelCtl *C, int p, bool lead, Round
         R.mode = kGather;
         R.level = plevel + 1;
     }
+    R.na = R.mode == kGather ? (R.cur ? na1 : na0) : 0;
     if (lead) {
-        C->mode[p] = R.mode;
-        C->level[p] = R.level;
-        C->cur[p] = R.cur;
-        C->ntc[q].v = 0;
-        C->rounds += 1;
-        if (pmode == kGather && nfp > 0) C->levels += 1;
-        if (R.mode == kNormal && R.level > C->max_level) C->max_level = R.level;
+        const u64 ntc_prev = prof ? ld(&C->ntc[q].v) : 0;
+        st(&C->mode[p], R.mode);
+        st(&C->level[p], R.level);
+        st(&C->cur[p], R.cur);
+        st(&C->ntc[q].v, (u64)0);
+        L.rounds += 1;
+        if (pmode == kGather && nfp > 0) L.levels += 1;
+        if (R.mode == kNormal && R.level > L.max_level) L.max_level = R.level;
+        if (prof) {
+            const u64 pt = ld(&C->push_twin[p].v), ps = ld(&C->push_surv[p].v);
+            st(&C->push_twin[p].v, (u64)0);
+            st(&C->push_surv[p].v, (u64)0);
+            st(&C->twin_pushes, ld(&C->twin_pushes) + pt);
+            st(&C->surv_pushes, ld(&C->surv_pushes) + ps);
+            if (pmode == kNormal && pt > 0 && ps == 0)
+                st(&C->twin_only_rounds, ld(&C->twin_only_rounds) + 1);
+            if (R.mode == kNormal) {
+                const int bnf = 63 - __clzll(nfp | 1);
+                st(&C->hist_nf[bnf], ld(&C->hist_nf[bnf]) + 1);
+            }
+            if (pmode == kNormal) {
+                const int bntc = 63 - __clzll(ntc_prev | 1);
+                st(&C->hist_ntc[bntc], ld(&C->hist_ntc[bntc]) + 1);
+            }
+        }
     }
     return true;
 }
@@ -218,33 +314,43 @@ __device__ __forceinline__ bool decide_round(PeelCtl *C, int p, bool lead, Round
 // Phase A.  Normal round: remove the frontier edges' wedges.  Gather round
 // (first round of a level): frontier = active edges with support <= level,
 // queued for the next round, while the active set is compacted into the
-// other buffer.  Work is spread over waves [wid, +nwaves).
+// other buffer.  Work is spread over waves [wid, +nwaves).  Memory
+// operations that do not depend on each other are issued together: a round
+// is a chain of dependent accesses, so the chain length sets its time.
 __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Round &R,
                                              int64_t wid, int64_t nwaves, u64 &upd) {
     PeelCtl *C = P.ctl;
     const int q = p ^ 1;
     const int32_t level = R.level;
     const int cur = R.cur;
-    const int32_t thresh = C->thresh;
+    const int32_t thresh = R.thresh;
     if (R.mode == kGather) {
-        const int64_t na = (int64_t)ld(&C->na[cur].v);
+        const int64_t na = (int64_t)R.na;
         int32_t mn = INT_MAX;
         for (int64_t i0 = wid * kWave; i0 < na; i0 += nwaves * kWave) {
             const int64_t i = i0 + lane_id();
             bool take = false, keep = false;
             int32_t e = 0;
             if (i < na) {
-                e = P.act[cur][i];
-                if (P.phi[e] < 0) {
-                    const int32_t sv = P.sup[e];
+                e = ld(&P.act[cur][i]);
+                const int32_t ph = ld(&P.phi[e]);
+                const int32_t sv = ld(&P.sup[e]);
+                if (ph < 0) {
                     take = sv <= level;
                     keep = !take;
                     if (keep) mn = min(mn, sv);
                 }
             }
-            push_front(take, e, P, q);
-            const u64 slot = wave_alloc(keep ? 1u : 0u, &C->na[cur ^ 1].v);
-            if (keep) P.act[cur ^ 1][slot] = e;
+            uint32_t lo = 0, hi = 0;
+            if (take) {
+                lo = (uint32_t)P.link_off[e];
+                hi = (uint32_t)P.link_off[(int64_t)e + 1];
+            }
+            const uint32_t k = take ? link_chunks(lo, hi) : 0u;
+            u64 base[3];
+            wave_alloc3(k, &C->nf[q].v, keep ? 1u : 0u, &C->na[cur ^ 1].v, 0u, nullptr, base);
+            put_front(P, q, base[0], e, lo, hi, k, level);
+            if (keep) st(&P.act[cur ^ 1][base[1]], e);
         }
         mn = wave_min(mn);
         if (lane_id() == 0 && mn != INT_MAX) atomicMin(&C->gmin[p], mn);
@@ -253,53 +359,56 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
     const int64_t nf = (int64_t)R.nf;
     int64_t i = wid;
     FrontItem it{};
-    if (i < nf) it = P.front[p][i];
+    if (i < nf) it = ld_item(&P.front[p][i]);
     while (i < nf) {
         const int64_t inext = i + nwaves;
         FrontItem nx{};
-        if (inext < nf) nx = P.front[p][inext];  // next item, loaded early
-        const int32_t e = it.e;
-        if (it.first && lane_id() == 0) P.phi[e] = level;
+        if (inext < nf) nx = ld_item(&P.front[p][inext]);  // next item, loaded early
         const uint32_t j = it.lo + lane_id();
-        const uint32_t l1 = it.hi;
-        bool won = false;
-        int32_t blm = 0, twin = 0, d = 0;
-        uint32_t w0 = 0, w1 = 0;
-        if (j < l1) {
-            const uint2 lk = P.link[j];
+        const bool has = j < it.hi;
+        uint32_t bit = 0, old = 0, w0 = 0, w1 = 0, tlo = 0, thi = 0;
+        int32_t blm = 0, twin = 0, kb = 0;
+        if (has) {
+            const uint3 lk = P.link[j];
             const uint32_t w = lk.x;
             blm = (int32_t)lk.y;
-            const uint32_t bit = 1u << (w & 31);
-            const uint32_t old = atomicAnd(&P.alive[w >> 5], ~bit);
-            const int32_t ea = P.wea[w], eb = P.web[w];
-            const int32_t kb = P.bk[blm];
-            const uint32_t b0 = P.bwoff[blm], b1 = P.bwoff[blm + 1];
-            if (old & bit) {
-                won = true;
-                twin = ea == e ? eb : ea;
-                d = kb - 1;
-                w0 = b0;
-                w1 = b1;
-            }
+            twin = (int32_t)lk.z;
+            bit = 1u << (w & 31);
+            w0 = P.bwoff[blm];
+            w1 = P.bwoff[blm + 1];
+            kb = ld(&P.bk[blm]);
+            // The twin's link range is fetched with the kill; it is used
+            // only if the twin drops to the level.
+            tlo = (uint32_t)P.link_off[twin];
+            thi = (uint32_t)P.link_off[(int64_t)twin + 1];
+            old = atomicAnd(&P.alive[w >> 5], ~bit);
         }
         // First kill in the bloom this round queues the bloom for phase B;
         // the twin loses its k - 1 butterflies in the bloom.
-        bool first = false;
-        int32_t otw = 0;
+        // A live wedge's bloom holds at least two live wedges, so d >= 1.
+        const bool won = has && (old & bit);
+        const int32_t d = max(kb - 1, 0);
         const bool dec = won && d > 0;
-        if (won) first = atomicAdd(&P.bc[blm], 1) == 0;
-        if (dec) otw = atomicSub(&P.sup[twin], d);
-        const uint32_t nch = first ? (w1 - w0 + kWedgeChunk - 1) / kWedgeChunk : 0u;
-        const u64 cbase = wave_alloc(nch, &C->ntc[p].v);
-        for (uint32_t c = 0; c < nch; ++c) {
-            const uint32_t a = w0 + c * kWedgeChunk;
-            P.tc[p][cbase + c] = BloomItem{blm, (int32_t)nch, a, min(a + (uint32_t)kWedgeChunk, w1)};
+        int32_t oc = 1, otw = 0;
+        if (won) {  // both atomics issue before either result is used
+            oc = atomicAdd(&P.bc[blm], 1);
+            otw = atomicSub(&P.sup[twin], d);
         }
+        const bool first = oc == 0;
+        const uint32_t nch = first ? (w1 - w0 + kWedgeChunk - 1) / kWedgeChunk : 0u;
         const bool tf = dec && otw > level && otw - d <= level;
         const bool ta = dec && otw >= thresh && otw - d < thresh;
-        push_front(tf, twin, P, q);
-        const u64 slot = wave_alloc(ta ? 1u : 0u, &C->na[cur].v);
-        if (ta) P.act[cur][slot] = twin;
+        const uint32_t tk = tf ? link_chunks(tlo, thi) : 0u;
+        if (P.prof) count_push(P, q, kSrcTwin, tf ? 1u : 0u);
+        u64 base[3];
+        wave_alloc3(nch, &C->ntc[p].v, tk, &C->nf[q].v, ta ? 1u : 0u, &C->na[cur].v, base);
+        for (uint32_t c = 0; c < nch; ++c) {
+            const uint32_t a = w0 + c * kWedgeChunk;
+            st_item(&P.tc[p][base[0] + c],
+                    BloomItem{blm, (int32_t)nch, a, min(a + (uint32_t)kWedgeChunk, w1)});
+        }
+        put_front(P, q, base[1], twin, tlo, thi, tk, level);
+        if (ta) st(&P.act[cur][base[2]], twin);
         upd += dec ? 1 : 0;
         it = nx;
         i = inext;
@@ -308,7 +417,9 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
 
 // Phase B: survivors of every touched bloom lose C[B]; the last chunk of a
 // bloom to finish sets k[B] -= C[B], C[B] = 0.  The lead clears counters
-// this round consumed (none of them is read in this phase).
+// this round consumed (none of them is read in this phase).  A decrement
+// that takes a support across the level queues the edge for the next
+// round; across the threshold, adds it to the active set.
 __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Round &R,
                                              int64_t wid, int64_t nwaves, bool lead, u64 &upd,
                                              u64 &visits) {
@@ -317,42 +428,74 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
     const int32_t level = R.level;
     const int cur = R.cur;
     if (lead) {
-        C->nf[p].v = 0;
-        C->gmin[q] = INT_MAX;
-        if (R.mode == kGather) C->na[cur].v = 0;  // compacted into the other buffer
+        st(&C->nf[p].v, (u64)0);
+        st(&C->gmin[q], (int32_t)INT_MAX);
+        if (R.mode == kGather) st(&C->na[cur].v, (u64)0);  // compacted into the other buffer
     }
     if (R.mode == kGather) return;
-    const int32_t thresh = C->thresh;
-    const int64_t ntc = (int64_t)ld(&C->ntc[p].v);
+    const int32_t thresh = R.thresh;
+    const int64_t ntc = (int64_t)R.ntc;
     int64_t i = wid;
     BloomItem it{};
-    if (i < ntc) it = P.tc[p][i];
+    if (i < ntc) it = ld_item(&P.tc[p][i]);
     while (i < ntc) {
         const int64_t inext = i + nwaves;
         BloomItem nx{};
-        if (inext < ntc) nx = P.tc[p][inext];  // next item, loaded early
+        if (inext < ntc) nx = ld_item(&P.tc[p][inext]);  // next item, loaded early
         const int32_t b = it.b;
         const uint32_t w = it.lo + lane_id();
         const bool inr = w < it.hi;
-        const uint32_t word = inr ? P.alive[w >> 5] : 0u;
+        uint32_t word = 0;
         int32_t ea = 0, eb = 0;
         if (inr) {
             ea = P.wea[w];
             eb = P.web[w];
+            word = ld(&P.alive[w >> 5]);
         }
-        const int32_t c = P.bc[b];
-        const int32_t kn = P.bk[b] - c;
+        const int32_t c = ld(&P.bc[b]);
+        const int32_t kn = ld(&P.bk[b]) - c;
         const bool live = inr && kn > 0 && ((word >> (w & 31)) & 1u);
-        dec_support2(live, ea, live, eb, c, level, thresh, P, q, cur);
+        int32_t o1 = 0, o2 = 0;
+        if (live) {
+            o1 = atomicSub(&P.sup[ea], c);
+            o2 = atomicSub(&P.sup[eb], c);
+        }
+        // The chunk counts itself done only once its reads of C[B] and k[B]
+        // have returned (the condition uses them), so the last chunk's
+        // update of both cannot overtake them.
+        bool last = false;
+        if (lane_id() == 0 && kn != INT_MIN)
+            last = it.nch == 1 || atomicAdd(&P.bdone[b], 1) == it.nch - 1;
+        const bool f1 = live && o1 > level && o1 - c <= level;
+        const bool f2 = live && o2 > level && o2 - c <= level;
+        const bool a1 = live && o1 >= thresh && o1 - c < thresh;
+        const bool a2 = live && o2 >= thresh && o2 - c < thresh;
+        uint32_t lo1 = 0, hi1 = 0, lo2 = 0, hi2 = 0;
+        if (f1) {
+            lo1 = (uint32_t)P.link_off[ea];
+            hi1 = (uint32_t)P.link_off[(int64_t)ea + 1];
+        }
+        if (f2) {
+            lo2 = (uint32_t)P.link_off[eb];
+            hi2 = (uint32_t)P.link_off[(int64_t)eb + 1];
+        }
+        const uint32_t k1 = f1 ? link_chunks(lo1, hi1) : 0u;
+        const uint32_t k2 = f2 ? link_chunks(lo2, hi2) : 0u;
+        if (P.prof) count_push(P, q, kSrcSurvivor, (f1 ? 1u : 0u) + (f2 ? 1u : 0u));
+        u64 base[3];
+        wave_alloc3(k1 + k2, &C->nf[q].v, (a1 ? 1u : 0u) + (a2 ? 1u : 0u), &C->na[cur].v, 0u,
+                    nullptr, base);
+        put_front(P, q, base[0], ea, lo1, hi1, k1, level);
+        put_front(P, q, base[0] + k1, eb, lo2, hi2, k2, level);
+        if (a1) st(&P.act[cur][base[1]], ea);
+        if (a2) st(&P.act[cur][base[1] + (a1 ? 1 : 0)], eb);
         upd += live ? 2 : 0;
         if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
-        if (lane_id() == 0) {
-            if (it.nch == 1 || atomicAdd(&P.bdone[b], 1) == it.nch - 1) {
-                P.bk[b] = kn;
-                P.bc[b] = 0;
-                P.bdone[b] = 0;
-                visits += 1;
-            }
+        if (last) {
+            st(&P.bk[b], kn);
+            st(&P.bc[b], 0);
+            st(&P.bdone[b], 0);
+            visits += 1;
         }
         it = nx;
         i = inext;
@@ -373,26 +516,44 @@ __device__ __forceinline__ void flush_stats(PeelCtl *C, u64 upd, u64 visits) {
 
 __global__ __launch_bounds__(kBlock) void k_phase_a(PeelArgs P, int p) {
     PeelCtl *C = P.ctl;
-    if (C->stall) return;
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    Round R;
-    if (!decide_round(C, p, lead, R)) return;
+    __shared__ Round sR;
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        const bool lead = blockIdx.x == 0;
+        LeadStats L{};
+        if (lead) L.load(C);
+        s_ok = !ld(&C->stall) && decide_round(C, p, lead, sR, L, P.prof);
+        if (lead) L.store(C);
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const Round R = sR;
     u64 upd = 0;
-    phase_a_work(P, p, R, blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave,
+    phase_a_work(P, p, R, (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x,
                  (int64_t)gridDim.x * kWavesPerBlock, upd);
     flush_stats(C, upd, 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
     PeelCtl *C = P.ctl;
-    if (C->stall) return;
-    Round R;
-    R.mode = C->mode[p];
-    R.level = C->level[p];
-    R.cur = C->cur[p];
-    R.nf = 0;
+    __shared__ Round sR;
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        s_ok = !ld(&C->stall);
+        if (s_ok) {
+            sR.mode = ld(&C->mode[p]);
+            sR.level = ld(&C->level[p]);
+            sR.cur = ld(&C->cur[p]);
+            sR.thresh = ld(&C->thresh);
+            sR.nf = sR.na = 0;
+            sR.ntc = ld(&C->ntc[p].v);
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const Round R = sR;
     u64 upd = 0, visits = 0;
-    phase_b_work(P, p, R, blockIdx.x * (int64_t)kWavesPerBlock + threadIdx.x / kWave,
+    phase_b_work(P, p, R, (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x,
                  (int64_t)gridDim.x * kWavesPerBlock, blockIdx.x == 0 && threadIdx.x == 0, upd,
                  visits);
     flush_stats(C, upd, visits);
@@ -403,80 +564,97 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
 constexpr int kPBlock = 512;
 
 struct GridBar {
-    Counter group[8];
-    Counter top;
-    Counter gen;
+    Counter group[8];  // arrivals per group (monotonic)
+    Counter top;       // completed groups (monotonic)
+    Counter rel[8];    // per-group release: the number of the last open barrier
     int32_t fail;
 };
 
-// Two-level barrier: blocks arrive at one of eight group counters, the last
-// of each group at the top counter, and the last of those opens the next
-// generation.  Release and acquire fences make every block's writes before
-// the barrier visible to every block after it.  A waiter gives up after a
-// bounded spin (the kernel then stops with `fail` set) so no bug can hang
-// the device.
-__device__ bool grid_sync(GridBar *B, u64 &gen_local) {
-    __shared__ int ok_s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        __threadfence();
-        const unsigned nb = gridDim.x;
-        const unsigned g = blockIdx.x & 7;
-        const unsigned ngroups = nb < 8 ? nb : 8;
-        const unsigned gsize = (nb - g + 7) / 8;
-        bool opener = false;
-        if (atomicAdd(&B->group[g].v, 1ull) == gsize - 1) {
-            __hip_atomic_store(&B->group[g].v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            if (atomicAdd(&B->top.v, 1ull) == ngroups - 1) {
-                __hip_atomic_store(&B->top.v, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __threadfence();
-                atomicAdd(&B->gen.v, 1ull);
-                opener = true;
-            }
+// Waits until this wave's memory operations have completed: its device-scope
+// stores and atomics have reached the point of coherence.
+__device__ __forceinline__ void drain_memory() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Two-level barrier, thread 0 of each block; `k` counts the barriers this
+// block has passed.  Blocks arrive at one of eight group counters (group g
+// holds the blocks of XCD g), the last of each group at the top counter; the
+// last of those writes the barrier's number to every group's release word,
+// and each block polls its own group's word, so no address takes the polls
+// of the whole grid.  Counters only grow, so nothing is reset between
+// barriers.  Shared state is only touched through device-scope accesses, so
+// draining every wave's outstanding operations before arrival (done by the
+// caller for all waves) orders them before the barrier, with no cache
+// write-back or invalidation.  A waiter gives up after a bounded spin (the
+// kernel then stops with `fail` set) so no bug can hang the device.
+__device__ bool grid_arrive_wait(GridBar *B, u64 &k) {
+    const unsigned nb = gridDim.x;
+    const unsigned g = blockIdx.x & 7;
+    const unsigned ngroups = nb < 8 ? nb : 8;
+    const unsigned gsize = (nb - g + 7) / 8;
+    k += 1;
+    if (atomicAdd(&B->group[g].v, 1ull) == k * gsize - 1) {
+        if (atomicAdd(&B->top.v, 1ull) == k * ngroups - 1) {
+            for (unsigned j = 0; j < ngroups; ++j) st(&B->rel[j].v, k);
         }
-        if (!opener) {
-            int64_t spins = 0;
-            while (ld(&B->gen.v) == gen_local) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (int64_t(1) << 28) || ld(&B->fail)) {
-                    __hip_atomic_store(&B->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        gen_local += 1;
-        __threadfence();
-        ok_s = ok;
     }
-    __syncthreads();
-    return ok_s != 0;
+    bool ok = true;
+    int64_t spins = 0;
+    while (ld(&B->rel[g].v) < k) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (int64_t(1) << 28) || ld(&B->fail)) {
+            st(&B->fail, 1);
+            ok = false;
+            break;
+        }
+    }
+    drain_memory();
+    return ok;
 }
 
 __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar *B,
                                                              int64_t max_rounds, int prof) {
     PeelCtl *C = P.ctl;
-    u64 gen_local = 0;
-    if (threadIdx.x == 0) gen_local = ld(&B->gen.v);
+    __shared__ Round sR;
+    __shared__ int s_ok;
+    u64 gen_local = 0;  // barriers passed (the host clears the barrier per launch)
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    const int64_t wid = blockIdx.x * (int64_t)(kPBlock / kWave) + threadIdx.x / kWave;
+    // Wave ids run across blocks first: a small round spreads its work items
+    // over many CUs (and all XCDs) instead of filling a few CUs' memory
+    // pipelines with scattered accesses.
+    const int64_t wid = (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
     const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
     int p = 0;
     u64 t[5] = {0, 0, 0, 0, 0}, acc[6] = {0, 0, 0, 0, 0, 0};
     u64 upd = 0, visits = 0;
-    for (int64_t r = 0; r < max_rounds; ++r) {
+    LeadStats L{};
+    if (lead) L.load(C);
+    if (threadIdx.x == 0) s_ok = decide_round(C, p, lead, sR, L, P.prof);
+    __syncthreads();
+    for (int64_t r = 0; r < max_rounds && s_ok; ++r) {
         if (prof && lead) t[0] = wall_clock64();
-        Round R;
-        if (!decide_round(C, p, lead, R)) break;
+        Round R = sR;
         phase_a_work(P, p, R, wid, nwaves, upd);
         if (prof && lead) t[1] = wall_clock64();
-        if (!grid_sync(B, gen_local)) break;
+        drain_memory();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_ok = grid_arrive_wait(B, gen_local);
+            sR.ntc = ld(&C->ntc[p].v);
+        }
+        __syncthreads();
+        if (!s_ok) break;
+        R.ntc = sR.ntc;
         if (prof && lead) t[2] = wall_clock64();
         phase_b_work(P, p, R, wid, nwaves, lead, upd, visits);
         if (prof && lead) t[3] = wall_clock64();
-        if (!grid_sync(B, gen_local)) break;
+        drain_memory();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_ok = grid_arrive_wait(B, gen_local) && decide_round(C, p ^ 1, lead, sR, L, P.prof);
+        }
+        __syncthreads();
         if (prof && lead) {
             t[4] = wall_clock64();
             for (int k = 0; k < 4; ++k) acc[k] += t[k + 1] - t[k];
@@ -489,8 +667,9 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     }
     flush_stats(C, upd, visits);
     if (lead) {
-        C->pad = p;
-        for (int k = 0; k < 6; ++k) C->prof[k] += acc[k];
+        L.store(C);
+        st(&C->pad, p);
+        for (int k = 0; k < 6; ++k) st(&C->prof[k], ld(&C->prof[k]) + acc[k]);
     }
 }
 
@@ -645,6 +824,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     P.act[0] = ws.get<int32_t>("peel_act0", m);
     P.act[1] = ws.get<int32_t>("peel_act1", m);
     P.ctl = ws.get<PeelCtl>("peel_ctl", 1);
+    P.prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
     int32_t *glist[2] = {ws.get<int32_t>("peel_all0", m), ws.get<int32_t>("peel_all1", m)};
     u64 *rs = ws.get<u64>("peel_refill", 40);  // [0] count, [1] min, [2..34] histogram
 
@@ -675,7 +855,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_persistent, kPBlock, 0));
         const char *pb = std::getenv("BT_PEEL_PBLOCKS");
-        pblocks = pb ? std::atoi(pb) : 96;
+        pblocks = pb ? std::atoi(pb) : cus;  // one block per CU
         pblocks = std::max(1, std::min(pblocks, occ * cus));
     }
 
@@ -752,6 +932,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             int64_t max_rounds = 4 * m + 64;
             int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
             void *args[] = {&P, &bar, &max_rounds, &prof};
+            BT_HIP(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
             BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
                                               dim3(kPBlock), args, 0, s));
         } else if (use_graph) {
@@ -790,6 +971,16 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         std::fprintf(stderr, "[peel] rounds %llu  block0 us: phaseA %.0f bar1 %.0f phaseB %.0f bar2 %.0f; gather rounds %llu phaseA+bar1 %.0f\n",
                      hc->rounds, hc->prof[0] / 100.0, hc->prof[1] / 100.0, hc->prof[2] / 100.0,
                      hc->prof[3] / 100.0, hc->prof[5], hc->prof[4] / 100.0);
+    if (P.prof) {
+        std::fprintf(stderr, "[peel] pushes: twin %llu survivor %llu; twin-only rounds %llu\n[peel] frontier items log2 histogram:",
+                     hc->twin_pushes, hc->surv_pushes, hc->twin_only_rounds);
+        for (int b = 0; b < 32; ++b)
+            if (hc->hist_nf[b]) std::fprintf(stderr, " %d:%llu", b, hc->hist_nf[b]);
+        std::fprintf(stderr, "\n[peel] bloom items log2 histogram:");
+        for (int b = 0; b < 32; ++b)
+            if (hc->hist_ntc[b]) std::fprintf(stderr, " %d:%llu", b, hc->hist_ntc[b]);
+        std::fprintf(stderr, "\n");
+    }
     k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);
     BT_CHECK_LAUNCH();
 }

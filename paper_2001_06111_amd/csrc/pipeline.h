@@ -55,7 +55,7 @@ struct IndexArrays {
     int32_t *wbl = nullptr;     // [cap_w] bloom of the wedge
     uint64_t *supl = nullptr;   // [m] (links << 32) | support while building
     int64_t *link_off = nullptr;  // [m + 1]
-    uint2 *link = nullptr;        // [2 cap_w] {wedge, bloom of the wedge}
+    uint3 *link = nullptr;        // [2 cap_w] {wedge, bloom of the wedge, twin edge}
     uint64_t *cursor = nullptr;   // device (blooms << 32) | wedges allocated
     int64_t *butterflies = nullptr;  // device scalar
 };

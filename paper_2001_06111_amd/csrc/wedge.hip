@@ -283,22 +283,22 @@ __global__ void k_link_counts(const uint64_t *supl, int64_t m, int32_t *cnt) {
         cnt[e] = (int32_t)(supl[e] >> 32);
 }
 
-// Scatter each wedge, with its bloom, into the link lists of its two edges.  The link count
-// in the high half of supl is consumed as a cursor (counting down).
+// Scatter each wedge, with its bloom and the edge's twin, into the link lists of its two
+// edges.  The link count in the high half of supl is consumed as a cursor (counting down).
 __global__ void k_link_scatter(const int32_t *wea, const int32_t *web, const int32_t *wbl,
                                const uint64_t *cursor, uint64_t *supl, const int64_t *link_off,
-                               uint2 *link) {
+                               uint3 *link) {
     const int64_t nw = (int64_t)(*cursor & 0xffffffffu);
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw;
          w += (int64_t)gridDim.x * blockDim.x) {
         const int32_t ea = wea[w], eb = web[w];
-        const uint2 entry = make_uint2((uint32_t)w, (uint32_t)wbl[w]);
+        const uint32_t b = (uint32_t)wbl[w];
         const uint64_t oa = atomicAdd((unsigned long long *)&supl[ea],
                                       (unsigned long long)(-(int64_t)(uint64_t(1) << 32)));
-        link[link_off[ea] + (int64_t)(oa >> 32) - 1] = entry;
+        link[link_off[ea] + (int64_t)(oa >> 32) - 1] = make_uint3((uint32_t)w, b, (uint32_t)eb);
         const uint64_t ob = atomicAdd((unsigned long long *)&supl[eb],
                                       (unsigned long long)(-(int64_t)(uint64_t(1) << 32)));
-        link[link_off[eb] + (int64_t)(ob >> 32) - 1] = entry;
+        link[link_off[eb] + (int64_t)(ob >> 32) - 1] = make_uint3((uint32_t)w, b, (uint32_t)ea);
     }
 }
 
