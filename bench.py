@@ -273,12 +273,12 @@ def peel_bytes(st, m):
 
     Per support decrement: a 4-byte read-modify-write (8 B).  Per link (each
     of the 2 n_W edge-wedge links is walked once, when its edge is removed):
-    the 8-byte link, the wedge's alive word (RMW, 8 B), its two edge ids
-    (8 B) and the bloom's k and wedge range (12 B).  Per touched-bloom
-    visit: its C and k (8 B) and the 16-byte work item (written, read).
-    Per edge: one frontier item (16 B written and read) and its phi (4 B).
+    the 12-byte link (wedge, bloom, twin edge), the wedge's alive word (RMW,
+    8 B) and the bloom's k and wedge range (12 B).  Per touched-bloom visit:
+    its C and k (8 B) and the 16-byte work item (written, read).  Per edge:
+    one frontier item (16 B written and read) and its phi (4 B).
     """
-    return (8 * st["support_updates"] + 36 * 2 * st["bloom_wedges"]
+    return (8 * st["support_updates"] + 32 * 2 * st["bloom_wedges"]
             + 40 * st["bloom_visits"] + 36 * m)
 
 

@@ -842,6 +842,8 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     u64 *hr = reinterpret_cast<u64 *>(hc + 1);
     // BT_PEEL_MODE=graph replays captured two-kernel rounds instead of the
     // persistent kernel; BT_PEEL_GRAPH=0 launches those rounds directly.
+    // BT_PEEL_VERBOSE=1 prints one line per persistent launch (long peels).
+    const bool verbose = std::getenv("BT_PEEL_VERBOSE") != nullptr;
     const char *mv = std::getenv("BT_PEEL_MODE");
     const bool persistent = ws.coop && !(mv && std::strcmp(mv, "graph") == 0);
     const char *gv = std::getenv("BT_PEEL_GRAPH");
@@ -957,6 +959,10 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             if (!hc->stall) throw Error{BT_EDEVICE, "peel stopped early"};
         }
         if (hc->stall) need_refill = true;
+        if (verbose && persistent)
+            std::fprintf(stderr, "[peel] launch %lld: %lld edges remained, level %d, rounds %llu, %.1f ms\n",
+                         (long long)pc.launches, (long long)n_all, hc->max_level, hc->rounds,
+                         (double)pc.kernel_ms);
         chunk = std::min(chunk * 2, 64);
         if (guard > 4 * m + 64) throw Error{BT_EDEVICE, "peel made no progress"};
     }

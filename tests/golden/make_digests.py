@@ -6,7 +6,7 @@ total and the generator version.  For the many-small-graphs pool the
 digest covers the concatenation of the per-graph arrays in pool order.
 Calls only `oracle` and the seeded generators.
 
-  python tests/golden/make_digests.py [uniform10k] [chunglu5m] [pool:N] [big:N]
+  python tests/golden/make_digests.py [uniform10k] [chunglu5m] [hub20m:sup] [pool:N] [big:N]
 """
 import hashlib
 import json
@@ -48,6 +48,17 @@ def main(args):
                             "phi_sha256": sha(phi), "max_phi": int(phi.max()) if g.m else 0,
                             "levels": st["levels"], "rounds": st["rounds"],
                             "oracle_seconds": round(dt, 1), "oracle_threads": oracle.max_threads(),
+                            "generator_version": synth.GENERATOR_VERSION}
+        elif a == "hub20m:sup":
+            # Support counting only: the oracle's peel would take hours here.
+            g = synth.plain_hub_20m()
+            t0 = time.time()
+            sup, bf, pairs = oracle.support(g.n_upper, g.n_lower, g.row_ptr, g.col)
+            assert bf == pairs
+            data[g.name] = {"m": g.m, "butterflies": bf, "sup_sha256": sha(sup),
+                            "max_sup": int(sup.max()) if g.m else 0,
+                            "oracle_support_seconds": round(time.time() - t0, 1),
+                            "oracle_threads": oracle.max_threads(),
                             "generator_version": synth.GENERATOR_VERSION}
         elif a.startswith("pool:") or a.startswith("big:"):
             kind, n = a.split(":")
