@@ -86,6 +86,7 @@ typedef struct bt_stats {
     float ms_peel;            /* peel */
     float ms_peel_kernel;     /* device time of the peel kernels alone (HIP events) */
     int32_t peel_launches;    /* peel kernel (or round-graph) launches */
+    int32_t passes;           /* subgraph passes (1, or BiT-PC's thresholds) */
 } bt_stats;
 
 /* Opaque device-resident BE-Index. */
@@ -148,6 +149,24 @@ void bt_index_free(bt_index *idx);
  */
 bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
                        bt_stats *stats, hipStream_t stream);
+
+/*
+ * Bitruss numbers by progressive compression, BiT-PC (Section V-C,
+ * Algorithms 6-7): for thresholds eps = k_max, k_max - alpha, ..., 0 with
+ * alpha = ceil(k_max * tau) and k_max the largest k such that k edges have
+ * support >= k, build the BE-Index of the subgraph of edges whose support in
+ * G is >= eps, with edges fixed by earlier thresholds kept in their blooms
+ * but never updated, and peel it, fixing the edges of the eps-bitruss.
+ * Results equal bt_decompose; fewer support updates on hub-heavy graphs.
+ *   tau      in (0, 1] (else BT_EINVAL); the paper suggests 0.05 - 0.2.
+ *   sup_out  device int64[m] (nullable): supports in G.
+ *   phi_out  device int64[m]: bitruss numbers.
+ *   stats    host (nullable): sums over the passes (passes = thresholds
+ *            whose subgraph held an unfixed edge; blooms and bloom_wedges
+ *            summed over passes, index_bytes the largest pass).
+ */
+bt_status bt_decompose_pc(const bt_csr *g, double tau, int64_t *sup_out, int64_t *phi_out,
+                          bt_stats *stats, hipStream_t stream);
 
 /*
  * Decompose many independent graphs in shared launches.  gs is a HOST

@@ -36,7 +36,8 @@ class bt_stats(ctypes.Structure):
         "butterflies", "wedges_po", "blooms", "bloom_wedges", "index_bytes", "levels",
         "rounds", "max_phi", "support_updates", "bloom_visits")] + [
         (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel",
-                                      "ms_peel_kernel")] + [("peel_launches", ctypes.c_int32)]
+                                      "ms_peel_kernel")] + [
+        ("peel_launches", ctypes.c_int32), ("passes", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -48,7 +49,8 @@ class bt_index_info(ctypes.Structure):
 
 
 EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
-            "bt_index_free", "bt_decompose", "bt_decompose_batch", "bt_release_workspace",
+            "bt_index_free", "bt_decompose", "bt_decompose_pc", "bt_decompose_batch",
+            "bt_release_workspace",
             "bt_last_error", "bt_version"]
 
 _lib = None
@@ -69,13 +71,15 @@ def load():
         L.bt_index_free.argtypes = [p]
         L.bt_index_free.restype = None
         L.bt_decompose.argtypes = [ctypes.POINTER(bt_csr), p, p, ctypes.POINTER(bt_stats), p]
+        L.bt_decompose_pc.argtypes = [ctypes.POINTER(bt_csr), ctypes.c_double, p, p,
+                                      ctypes.POINTER(bt_stats), p]
         L.bt_decompose_batch.argtypes = [ctypes.POINTER(bt_csr), i32, ctypes.POINTER(p),
                                          ctypes.POINTER(p), ctypes.POINTER(bt_stats), p]
         L.bt_release_workspace.restype = None
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
         for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
-                     "bt_decompose", "bt_decompose_batch"):
+                     "bt_decompose", "bt_decompose_pc", "bt_decompose_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -143,6 +147,22 @@ def bt_decompose(g: DeviceGraph, want_sup: bool = True, stats: bool = False, str
     c = g.csr()
     _check(L.bt_decompose(ctypes.byref(c), _ptr(sup), _ptr(phi),
                           ctypes.byref(st) if stats else None, _stream(stream)))
+    return sup, phi, (st.as_dict() if stats else None)
+
+
+def bt_decompose_pc(g: DeviceGraph, tau: float = 0.1, want_sup: bool = True, stats: bool = False,
+                    stream=None, out_phi: torch.Tensor | None = None,
+                    out_sup: torch.Tensor | None = None):
+    """BiT-PC: (supports or None, bitruss numbers, stats dict or None)."""
+    L = load()
+    dev = g.col.device
+    phi = out_phi if out_phi is not None else torch.empty(g.m, dtype=torch.int64, device=dev)
+    sup = out_sup if out_sup is not None else (
+        torch.empty(g.m, dtype=torch.int64, device=dev) if want_sup else None)
+    st = bt_stats()
+    c = g.csr()
+    _check(L.bt_decompose_pc(ctypes.byref(c), ctypes.c_double(tau), _ptr(sup), _ptr(phi),
+                             ctypes.byref(st) if stats else None, _stream(stream)))
     return sup, phi, (st.as_dict() if stats else None)
 
 

@@ -1,4 +1,5 @@
 // api.hip - the C ABI: argument checks, workspace, stage orchestration.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <mutex>
@@ -148,6 +149,7 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->ms_peel = ev.ms(3, 4);
     stats->ms_peel_kernel = (float)pc.kernel_ms;
     stats->peel_launches = (int32_t)pc.launches;
+    stats->passes = 1;
 }
 
 }  // namespace
@@ -167,6 +169,101 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
     BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     BT_HIP(hipStreamSynchronize(stream));
     if (stats) fill_stats(stats, r, ix, pc, g.m, hs[0], ev);
+}
+
+// BiT-PC (Section V-C, Algorithm 7).  Supports in G and k_max; then for
+// eps = k_max, k_max - alpha, ..., 0 (alpha = ceil(k_max tau)): the
+// subgraph G_{>=eps}, its BE-Index with the already fixed edges marked
+// (Algorithm 6), and a peel whose first level is eps - 1, so that one level
+// removes every edge outside the eps-bitruss (whose numbers are < eps and
+// left for later passes) and the levels from eps up fix the numbers of the
+// eps-bitruss.  Algorithm 7's single recount-and-drop of edges below eps is
+// subsumed by that first level, which repeats it to the fixpoint.
+void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *phi_out,
+                       bt_stats *stats, Workspace &ws, hipStream_t s) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    const int64_t m = g.m;
+    Events ev(stats != nullptr, s);
+    ev.mark(0);
+    RankCSR r;
+    prepare(g, r, ws, s);
+    TaskLists t;
+    make_tasks(r, t, ws, s);
+    ev.mark(1);
+    uint64_t *supl = ws.get<uint64_t>("pc_supl", m + 1);
+    int64_t *bf = ws.get<int64_t>("pc_bf", 2);
+    BT_HIP(hipMemsetAsync(supl, 0, sizeof(uint64_t) * (m + 1), s));
+    BT_HIP(hipMemsetAsync(bf, 0, sizeof(int64_t) * 2, s));
+    count_support(r, t, supl, bf, s);
+    if (sup_out && m) supl_to_sup(supl, sup_out, m, s);
+    int32_t *sup0 = ws.get<int32_t>("pc_sup0", m);
+    const int32_t kmax = pc_kmax(supl, m, sup0, ws, s);
+    ev.mark(2);
+    int64_t *hs = ws.host(2);
+    BT_HIP(hipMemcpyAsync(hs, bf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipStreamSynchronize(s));
+    const int64_t butterflies = hs[0];
+    const int64_t wedges_po = r.wedges_po;
+    int32_t *phi_glob = ws.get<int32_t>("pc_phi", m);
+    int64_t *phi_sub = ws.get<int64_t>("pc_phisub", m);
+    if (m) fill_i32(phi_glob, -1, m, s);
+    const int32_t alpha =
+        std::max<int32_t>(1, (int32_t)std::min<double>(std::ceil(kmax * tau), INT32_MAX));
+    PeelCounters tot;
+    int64_t blooms = 0, bloom_wedges = 0, idx_bytes = 0;
+    int32_t passes = 0;
+    for (int32_t eps = kmax; m > 0;) {
+        PcSubgraph sg;
+        pc_subgraph(g, sup0, eps, phi_glob, sg, ws, s);
+        if (sg.open > 0) {
+            RankCSR rs;
+            IndexArrays ix;
+            build_all(sg.g, rs, ix, false, nullptr, ws, s, nullptr);
+            mark_fixed(ix, sg.fixed, s);
+            PeelOptions o;
+            o.fixed = sg.fixed;
+            o.min_level = eps > 0 ? eps - 1 : 0;
+            PeelCounters pc;
+            peel(rs, ix, nullptr, phi_sub, pc, ws, s, &o);
+            pc_collect(phi_sub, sg, eps, phi_glob, s);
+            tot.levels += pc.levels;
+            tot.rounds += pc.rounds;
+            if (pc.max_phi >= eps) tot.max_phi = std::max(tot.max_phi, pc.max_phi);
+            tot.updates += pc.updates;
+            tot.bloom_visits += pc.bloom_visits;
+            tot.kernel_ms += pc.kernel_ms;
+            tot.launches += pc.launches;
+            blooms += ix.n_b;
+            bloom_wedges += ix.n_w;
+            idx_bytes = std::max(idx_bytes, index_bytes(ix, sg.g.m));
+            passes += 1;
+        }
+        if (eps == 0) break;
+        eps = std::max(eps - alpha, 0);
+    }
+    pc_widen(phi_glob, m, phi_out, s);
+    ev.mark(3);
+    ev.mark(4);
+    BT_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        stats->butterflies = butterflies;
+        stats->wedges_po = wedges_po;
+        stats->blooms = blooms;
+        stats->bloom_wedges = bloom_wedges;
+        stats->index_bytes = idx_bytes;
+        stats->levels = tot.levels;
+        stats->rounds = tot.rounds;
+        stats->max_phi = tot.max_phi;
+        stats->support_updates = tot.updates;
+        stats->bloom_visits = tot.bloom_visits;
+        stats->ms_prepare = ev.ms(0, 1);
+        stats->ms_count = ev.ms(1, 2);
+        stats->ms_link = 0.f;
+        stats->ms_peel = ev.ms(2, 3);  // every pass: subgraph, index, peel
+        stats->ms_peel_kernel = (float)tot.kernel_ms;
+        stats->peel_launches = (int32_t)tot.launches;
+        stats->passes = passes;
+    }
 }
 
 namespace {
@@ -245,6 +342,7 @@ void add_stats(bt_stats &t, const bt_stats &s) {
     t.ms_peel += s.ms_peel;
     t.ms_peel_kernel += s.ms_peel_kernel;
     t.peel_launches += s.peel_launches;
+    t.passes = std::max(t.passes, s.passes);
 }
 
 // Graphs [a, b) as one union; splits the range if the union is too large.
@@ -461,6 +559,17 @@ bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out, bt_s
         if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
         std::lock_guard<std::mutex> lk(lib().mu);
         decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream);
+    });
+}
+
+bt_status bt_decompose_pc(const bt_csr *g, double tau, int64_t *sup_out, int64_t *phi_out,
+                          bt_stats *stats, hipStream_t stream) {
+    return guard([&] {
+        check_graph(g);
+        if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
+        if (!(tau > 0.0 && tau <= 1.0)) throw Error{BT_EINVAL, "tau must lie in (0, 1]"};
+        std::lock_guard<std::mutex> lk(lib().mu);
+        decompose_pc_impl(*g, tau, sup_out, phi_out, stats, lib().ws, stream);
     });
 }
 

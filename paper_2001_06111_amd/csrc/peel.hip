@@ -56,6 +56,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLinkChunk = kWave;   // links per phase-A work item (one per lane)
+// Progressive mode: edge ids in wedge records and link twins carry this bit
+// when the edge's bitruss number was fixed in an earlier pass; such edges
+// keep their blooms alive but are never decremented or removed.
+constexpr uint32_t kFixedBit = 0x80000000u;
+constexpr uint32_t kEdgeMask = 0x7fffffffu;
 constexpr int kWedgeChunk = kWave;  // wedges per phase-B work item (one per lane)
 int grid_a() {
     static int g = std::getenv("BT_PEEL_GRID_A") ? std::atoi(std::getenv("BT_PEEL_GRID_A")) : 2048;
@@ -207,13 +212,40 @@ __device__ __forceinline__ uint32_t link_chunks(uint32_t lo, uint32_t hi) {
 // the level of the round that removes it (a queued frontier keeps the
 // level), and only a gather, which runs once the frontier is empty, reads
 // phi while the peel runs.
+// Writes the cnt 64-element chunks of a lane's range [lo, hi) as items
+// {id, aux, a, min(a + 64, hi)} at slots base, base + 1, ...  A lane writes
+// up to kOwnChunks of its own; the rest of a longer range is written by the
+// whole wave, 64 chunks at a time, so a hub edge or a large bloom does not
+// hold up its wave (and the round) with thousands of serial stores.  All 64
+// lanes must call.
+constexpr uint32_t kOwnChunks = 4;
+template <typename Item>
+__device__ __forceinline__ void put_chunks(Item *list, u64 base, uint32_t cnt, int32_t id,
+                                           int32_t aux, uint32_t lo, uint32_t hi) {
+    const uint32_t own = min(cnt, kOwnChunks);
+    for (uint32_t c = 0; c < own; ++c) {
+        const uint32_t a = lo + c * kWave;
+        st_item(&list[base + c], Item{id, aux, a, min(a + (uint32_t)kWave, hi)});
+    }
+    unsigned long long big = __ballot(cnt > own);
+    while (big) {
+        const int l = __ffsll(big) - 1;
+        big &= big - 1;
+        const uint32_t n = __shfl(cnt, l, kWave);
+        const u64 b = __shfl(base, l, kWave);
+        const int32_t lid = __shfl(id, l, kWave), laux = __shfl(aux, l, kWave);
+        const uint32_t llo = __shfl(lo, l, kWave), lhi = __shfl(hi, l, kWave);
+        for (uint32_t c = kOwnChunks + lane_id(); c < n; c += kWave) {
+            const uint32_t a = llo + c * kWave;
+            st_item(&list[b + c], Item{lid, laux, a, min(a + (uint32_t)kWave, lhi)});
+        }
+    }
+}
+
 __device__ __forceinline__ void put_front(const PeelArgs &P, int q, u64 base, int32_t e,
                                           uint32_t lo, uint32_t hi, uint32_t k, int32_t level) {
     if (k) st(&P.phi[e], level);
-    for (uint32_t c = 0; c < k; ++c) {
-        const uint32_t a = lo + c * kLinkChunk;
-        st_item(&P.front[q][base + c], FrontItem{e, 0, a, min(a + (uint32_t)kLinkChunk, hi)});
-    }
+    put_chunks(P.front[q], base, k, e, 0, lo, hi);
 }
 
 enum : int { kSrcTwin = 0, kSrcSurvivor = 1 };
@@ -368,11 +400,13 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
         const bool has = j < it.hi;
         uint32_t bit = 0, old = 0, w0 = 0, w1 = 0, tlo = 0, thi = 0;
         int32_t blm = 0, twin = 0, kb = 0;
+        bool tfix = false;
         if (has) {
             const uint3 lk = P.link[j];
             const uint32_t w = lk.x;
             blm = (int32_t)lk.y;
-            twin = (int32_t)lk.z;
+            twin = (int32_t)(lk.z & kEdgeMask);
+            tfix = (lk.z & kFixedBit) != 0;
             bit = 1u << (w & 31);
             w0 = P.bwoff[blm];
             w1 = P.bwoff[blm + 1];
@@ -388,11 +422,11 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
         // A live wedge's bloom holds at least two live wedges, so d >= 1.
         const bool won = has && (old & bit);
         const int32_t d = max(kb - 1, 0);
-        const bool dec = won && d > 0;
+        const bool dec = won && d > 0 && !tfix;
         int32_t oc = 1, otw = 0;
         if (won) {  // both atomics issue before either result is used
             oc = atomicAdd(&P.bc[blm], 1);
-            otw = atomicSub(&P.sup[twin], d);
+            if (!tfix) otw = atomicSub(&P.sup[twin], d);
         }
         const bool first = oc == 0;
         const uint32_t nch = first ? (w1 - w0 + kWedgeChunk - 1) / kWedgeChunk : 0u;
@@ -402,11 +436,7 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
         if (P.prof) count_push(P, q, kSrcTwin, tf ? 1u : 0u);
         u64 base[3];
         wave_alloc3(nch, &C->ntc[p].v, tk, &C->nf[q].v, ta ? 1u : 0u, &C->na[cur].v, base);
-        for (uint32_t c = 0; c < nch; ++c) {
-            const uint32_t a = w0 + c * kWedgeChunk;
-            st_item(&P.tc[p][base[0] + c],
-                    BloomItem{blm, (int32_t)nch, a, min(a + (uint32_t)kWedgeChunk, w1)});
-        }
+        put_chunks(P.tc[p], base[0], nch, blm, (int32_t)nch, w0, w1);
         put_front(P, q, base[1], twin, tlo, thi, tk, level);
         if (ta) st(&P.act[cur][base[2]], twin);
         upd += dec ? 1 : 0;
@@ -445,20 +475,21 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         const int32_t b = it.b;
         const uint32_t w = it.lo + lane_id();
         const bool inr = w < it.hi;
-        uint32_t word = 0;
-        int32_t ea = 0, eb = 0;
+        uint32_t word = 0, ra = 0, rb = 0;
         if (inr) {
-            ea = P.wea[w];
-            eb = P.web[w];
+            ra = (uint32_t)P.wea[w];
+            rb = (uint32_t)P.web[w];
             word = ld(&P.alive[w >> 5]);
         }
+        const int32_t ea = (int32_t)(ra & kEdgeMask), eb = (int32_t)(rb & kEdgeMask);
         const int32_t c = ld(&P.bc[b]);
         const int32_t kn = ld(&P.bk[b]) - c;
         const bool live = inr && kn > 0 && ((word >> (w & 31)) & 1u);
+        const bool da = live && !(ra & kFixedBit), db = live && !(rb & kFixedBit);
         int32_t o1 = 0, o2 = 0;
         if (live) {
-            o1 = atomicSub(&P.sup[ea], c);
-            o2 = atomicSub(&P.sup[eb], c);
+            if (da) o1 = atomicSub(&P.sup[ea], c);
+            if (db) o2 = atomicSub(&P.sup[eb], c);
         }
         // The chunk counts itself done only once its reads of C[B] and k[B]
         // have returned (the condition uses them), so the last chunk's
@@ -466,10 +497,10 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         bool last = false;
         if (lane_id() == 0 && kn != INT_MIN)
             last = it.nch == 1 || atomicAdd(&P.bdone[b], 1) == it.nch - 1;
-        const bool f1 = live && o1 > level && o1 - c <= level;
-        const bool f2 = live && o2 > level && o2 - c <= level;
-        const bool a1 = live && o1 >= thresh && o1 - c < thresh;
-        const bool a2 = live && o2 >= thresh && o2 - c < thresh;
+        const bool f1 = da && o1 > level && o1 - c <= level;
+        const bool f2 = db && o2 > level && o2 - c <= level;
+        const bool a1 = da && o1 >= thresh && o1 - c < thresh;
+        const bool a2 = db && o2 >= thresh && o2 - c < thresh;
         uint32_t lo1 = 0, hi1 = 0, lo2 = 0, hi2 = 0;
         if (f1) {
             lo1 = (uint32_t)P.link_off[ea];
@@ -489,7 +520,7 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         put_front(P, q, base[0] + k1, eb, lo2, hi2, k2, level);
         if (a1) st(&P.act[cur][base[1]], ea);
         if (a2) st(&P.act[cur][base[1] + (a1 ? 1 : 0)], eb);
-        upd += live ? 2 : 0;
+        upd += (da ? 1 : 0) + (db ? 1 : 0);
         if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
         if (last) {
             st(&P.bk[b], kn);
@@ -561,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
 
 // --- persistent cooperative kernel: rounds separated by grid barriers ---
 
-constexpr int kPBlock = 512;
+constexpr int kPBlock = 1024;  // 16 waves per CU (108 VGPRs fit four waves per SIMD)
 
 struct GridBar {
     Counter group[8];  // arrivals per group (monotonic)
@@ -731,13 +762,17 @@ __global__ __launch_bounds__(kBlock) void k_refill_gather(const int32_t *list, i
     }
 }
 
-__global__ void k_init_peel(const uint64_t *supl, int64_t m, int32_t *sup, int32_t *phi,
-                            int64_t *sup_out) {
+// Edges whose bitruss number is already fixed (progressive mode) start
+// removed-looking (phi >= 0) with an unreachable support, so no gather,
+// refill or crossing ever takes them.
+__global__ void k_init_peel(const uint64_t *supl, int64_t m, const int32_t *fixed, int32_t *sup,
+                            int32_t *phi, int64_t *sup_out) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t s = (int32_t)(supl[e] & 0xffffffffu);
-        sup[e] = s;
-        phi[e] = -1;
+        const bool fx = fixed && fixed[e];
+        sup[e] = fx ? INT_MAX : s;
+        phi[e] = fx ? INT_MAX : -1;
         if (sup_out) sup_out[e] = s;
     }
 }
@@ -794,7 +829,9 @@ hipGraphExec_t chunk_graph(const PeelArgs &P, int rounds, Workspace &ws) {
 }  // namespace
 
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
-          PeelCounters &pc, Workspace &ws, hipStream_t s) {
+          PeelCounters &pc, Workspace &ws, hipStream_t s, const PeelOptions *opt) {
+    const int32_t *fixed = opt ? opt->fixed : nullptr;
+    const int32_t min_level = opt ? opt->min_level : 0;
     const int64_t m = r.m;
     if (m == 0) return;
     if (2 * ix.n_w >= (int64_t)UINT32_MAX)
@@ -828,7 +865,8 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     int32_t *glist[2] = {ws.get<int32_t>("peel_all0", m), ws.get<int32_t>("peel_all1", m)};
     u64 *rs = ws.get<u64>("peel_refill", 40);  // [0] count, [1] min, [2..34] histogram
 
-    k_init_peel<<<grid_for(m, 256, 16384), 256, 0, s>>>(ix.supl, m, P.sup, P.phi, sup_out);
+    k_init_peel<<<grid_for(m, 256, 16384), 256, 0, s>>>(ix.supl, m, fixed, P.sup, P.phi,
+                                                         sup_out);
     BT_CHECK_LAUNCH();
     k_init_alive<<<grid_for(words, 256, 16384), 256, 0, s>>>(ix.cursor, P.alive);
     BT_CHECK_LAUNCH();
@@ -892,9 +930,13 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             cur = nxt;
             n_all = (int64_t)hr[0];
             if (n_all == 0) break;
-            const int32_t mn = *reinterpret_cast<int32_t *>(hr + 1);
+            // The first level is at least min_level: every edge at or below
+            // it goes in one level (progressive mode), and the active set
+            // must then hold all of them.
+            const int32_t mn0 = *reinterpret_cast<int32_t *>(hr + 1);
+            const int32_t mn = std::max(mn0, min_level);
             k_refill_hist<<<grid_for(n_all, kBlock, 2048), kBlock, 0, s>>>(glist[cur], n_all,
-                                                                          P.sup, mn, rs + 2);
+                                                                          P.sup, mn0, rs + 2);
             BT_CHECK_LAUNCH();
             BT_HIP(hipMemcpyAsync(hr + 2, rs + 2, 33 * sizeof(u64), hipMemcpyDeviceToHost, s));
             BT_HIP(hipStreamSynchronize(s));
@@ -903,10 +945,11 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             for (int b = 0; b < 33; ++b) {
                 acc += (int64_t)hr[2 + b];
                 if (acc >= target) {
-                    thresh = std::min<int64_t>((int64_t)mn + (int64_t(2) << b) - 1, INT_MAX);
+                    thresh = std::min<int64_t>((int64_t)mn0 + (int64_t(2) << b) - 1, INT_MAX);
                     break;
                 }
             }
+            thresh = std::max<int64_t>(thresh, std::min<int64_t>((int64_t)mn + 1, INT_MAX));
             BT_HIP(hipMemsetAsync(&P.ctl->na[0].v, 0, sizeof(u64), s));
             k_refill_gather<<<grid_for(n_all, kBlock, 4096), kBlock, 0, s>>>(
                 glist[cur], n_all, P.sup, (int32_t)thresh, P.act[0], &P.ctl->na[0].v);

@@ -84,8 +84,18 @@ struct PeelCounters {
     double kernel_ms = 0;  // HIP-event time of the peel kernel launches
     int64_t launches = 0;
 };
+// Progressive mode (Section V-C): `fixed` (per edge, nullable) marks edges
+// whose bitruss numbers an earlier pass fixed; the index must carry their
+// marks (mark_fixed).  The first level is at least `min_level`.
+struct PeelOptions {
+    const int32_t *fixed = nullptr;
+    int32_t min_level = 0;
+};
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
-          PeelCounters &pc, Workspace &ws, hipStream_t s);
+          PeelCounters &pc, Workspace &ws, hipStream_t s, const PeelOptions *opt = nullptr);
+
+// Sets the fixed-edge mark in wedge records and link twins (progressive mode).
+void mark_fixed(IndexArrays &ix, const int32_t *fixed, hipStream_t s);
 
 // Whole decompositions (api.hip): one graph, or many as disjoint unions.
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
@@ -93,6 +103,25 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
 void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
                           hipStream_t s);
+// BiT-PC steps (pc.hip).  A pass's subgraph G_{>=eps}: the edges of g with
+// support >= eps in g, in g's order; orig maps them back, fixed marks those
+// whose bitruss numbers earlier passes fixed, open counts the others.
+struct PcSubgraph {
+    bt_csr g{};
+    int64_t *row_ptr = nullptr;
+    int32_t *col = nullptr, *orig = nullptr, *fixed = nullptr;
+    int64_t open = 0;
+};
+// Supports (low halves of supl) into sup0; returns k_max.
+int32_t pc_kmax(const uint64_t *supl, int64_t m, int32_t *sup0, Workspace &ws, hipStream_t s);
+int64_t pc_subgraph(const bt_csr &g, const int32_t *sup0, int32_t eps, const int32_t *phi_glob,
+                    PcSubgraph &sg, Workspace &ws, hipStream_t s);
+void pc_collect(const int64_t *phi_sub, const PcSubgraph &sg, int32_t eps, int32_t *phi_glob,
+                hipStream_t s);
+void pc_widen(const int32_t *phi_glob, int64_t m, int64_t *phi_out, hipStream_t s);
+// BiT-PC (Algorithms 6-7): progressive compression with step ceil(k_max tau).
+void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *phi_out,
+                       bt_stats *stats, Workspace &ws, hipStream_t s);
 void check_graph(const bt_csr *g);
 
 // Device-memory estimate of decomposing g (validates g; BT_EINVAL if
