@@ -225,7 +225,7 @@ def serve_compare(seconds, n_small, n_big, rate=200.0):
     lat_plain = done_plain - arrive
 
     # served: submit at arrival times, poll completions
-    eng = binding.BtEngine(slots=2)
+    eng = binding.BtEngine()
     done_srv = np.zeros(len(reqs))
     t0 = time.perf_counter()
     finished = threading.Event()

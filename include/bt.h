@@ -181,10 +181,12 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
 /*
  * Serving engine with continuous batching (for request streams).
  *
- * bt_engine_create: `slots` worker slots (0: 2), each with its own HIP
+ * bt_engine_create: `slots` worker slots (0: 1), each with its own HIP
  *   stream and workspace; `hbm_budget` bytes of device memory for requests
  *   in flight (0: half of the free memory); at most `max_batch` requests
- *   per batch (0: 1024).
+ *   per batch (0: 1024).  The peel of a batch holds the whole GPU, so the
+ *   peels of different slots take turns; more slots overlap only the other
+ *   stages.
  * bt_engine_submit: queue one request.  Validates the graph and estimates
  *   its device memory on the device (index and peel state bounded through
  *   the wedge bound of Lemma 6, sum over edges of min(d(u), d(v)), plus
@@ -192,10 +194,12 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   estimate exceeds the whole budget.  Graph and outputs are caller-owned
  *   DEVICE memory that must stay valid until the request completes;
  *   sup_out may be NULL.  Results equal bt_decompose on the same graph.
- * A free slot admits, in arrival order, every queued request that fits
- *   the budget left by the other slots and decomposes them as one batch
- *   (bt_decompose_batch semantics); requests that arrive meanwhile go to
- *   the next free slot, so batches overlap on the device.
+ * A free slot admits, in arrival order, queued requests of the class of
+ *   the oldest one that fit the budget left by the other slots, and
+ *   decomposes them as one batch (bt_decompose_batch semantics): a request
+ *   of at least 2^19 edges runs alone; smaller ones are batched together and
+ *   passed over larger ones.  Requests that arrive meanwhile go to the next
+ *   free slot, so batches overlap on the device.
  * bt_engine_poll: moves up to `cap` completed (id, status) pairs to the
  *   caller's host arrays; *n_done receives how many.
  * bt_engine_drain: blocks until every submitted request has completed.

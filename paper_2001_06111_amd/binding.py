@@ -267,7 +267,7 @@ class BtEngine:
     """bt_engine_* handle.  Keeps each request's graph and outputs alive until
     it completes; results are device tensors."""
 
-    def __init__(self, hbm_budget: int = 0, slots: int = 2, max_batch: int = 1024):
+    def __init__(self, hbm_budget: int = 0, slots: int = 1, max_batch: int = 1024):
         L = _engine_lib()
         self._h = ctypes.c_void_p(0)
         _check(L.bt_engine_create(int(hbm_budget), int(slots), int(max_batch),

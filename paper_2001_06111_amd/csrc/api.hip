@@ -1,5 +1,6 @@
 // api.hip - the C ABI: argument checks, workspace, stage orchestration.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <mutex>
@@ -266,6 +267,38 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
     }
 }
 
+constexpr int64_t kMultiMaxEdges = int64_t(1) << 19;
+
+// A disjoint union of graphs (edge ranges [off[g], off[g+1])): one index
+// build for the union, then one peel in which every graph has its own level.
+void decompose_union_impl(const bt_csr &u, const std::vector<int64_t> &off, int64_t *sup_out,
+                          int64_t *phi_out, bt_stats *stats, Workspace &ws, hipStream_t s) {
+    Events ev(stats != nullptr, s);
+    ev.mark(0);
+    RankCSR r;
+    IndexArrays ix;
+    build_all(u, r, ix, false, nullptr, ws, s, &ev);
+    ev.mark(3);
+    PeelCounters pc;
+    // Per-graph levels pay when there are several graphs, all small: its
+    // gathers rescan a graph's whole edge range, where the shared-level peel
+    // keeps a threshold active set.  BT_BATCH_PEEL=union forces the latter.
+    int64_t max_m = 0;
+    for (size_t g = 0; g + 1 < off.size(); ++g) max_m = std::max(max_m, off[g + 1] - off[g]);
+    const char *mode = std::getenv("BT_BATCH_PEEL");
+    const bool multi = ws.coop && off.size() > 2 && max_m <= kMultiMaxEdges &&
+                       !(mode && std::strcmp(mode, "union") == 0);
+    if (multi)
+        peel_multi(r, ix, sup_out, phi_out, off, pc, ws, s);
+    else
+        peel(r, ix, sup_out, phi_out, pc, ws, s);
+    ev.mark(4);
+    int64_t *hs = ws.host(2);
+    BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipStreamSynchronize(s));
+    if (stats) fill_stats(stats, r, ix, pc, u.m, hs[0], ev);
+}
+
 namespace {
 
 // ---- batches: many graphs decomposed as one disjoint union --------------
@@ -393,9 +426,12 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
     BT_HIP(hipStreamSynchronize(s));
     if (hf) throw Error{BT_EINVAL, "a graph of the batch is malformed"};
     const bt_csr u{(int32_t)nu, (int32_t)nl, m, row_ptr_u, col_u};
+    std::vector<int64_t> off(b - a + 1);
+    for (int32_t i = a; i < b; ++i) off[i - a] = tab[i - a].m_off;
+    off[b - a] = m;
     bt_stats st;
     try {
-        decompose_impl(u, sup_u, phi_u, stats ? &st : nullptr, ws, s);
+        decompose_union_impl(u, off, sup_u, phi_u, stats ? &st : nullptr, ws, s);
     } catch (const Error &e) {
         if (e.status != BT_EOVERFLOW || !splittable) throw;
         const int32_t mid = a + (b - a) / 2;

@@ -3,11 +3,14 @@
 // Requests (device CSRs with caller-owned outputs) are queued with a
 // device-memory estimate taken at submit time.  Each worker slot owns a HIP
 // stream and a workspace; when a slot is free it admits, in arrival order,
-// every queued request whose estimate still fits the engine's memory
-// budget (less what the other slots hold) and decomposes them together as
-// one disjoint union.  Requests that arrive while batches run are admitted
-// by the next free slot, so batches on different slots overlap on the GPU.
-// Each result equals the plain single-graph decomposition of the request.
+// queued requests of the class of the oldest one while their estimates fit
+// the engine's memory budget (less what the other slots hold), and
+// decomposes them together as one disjoint union.  A large request (at
+// least kLargeEdges edges) runs alone; small requests are batched together
+// and passed over large ones, so they do not wait for a large request's
+// peel.  Requests that arrive while batches run are admitted by the next
+// free slot, so batches on different slots overlap on the GPU.  Each result
+// equals the plain single-graph decomposition of the request.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -33,6 +36,8 @@ struct Done {
     uint64_t id;
     bt_status st;
 };
+
+constexpr int64_t kLargeEdges = int64_t(1) << 19;
 
 }  // namespace
 }  // namespace bt
@@ -64,8 +69,7 @@ void bt_engine::worker_loop(int slot) {
     (void)hipSetDevice(device);
     hipStream_t s = nullptr;
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    Workspace ws;
-    ws.coop = false;  // slots overlap: the peel must not wait on co-resident blocks
+    Workspace ws;  // cooperative peels of different slots take turns (see peel.hip)
     (void)slot;
     while (true) {
         std::vector<Request> batch;
@@ -77,12 +81,19 @@ void bt_engine::worker_loop(int slot) {
                 return !queue.empty() && reserved + queue.front().bytes <= budget;
             });
             if (stop) break;  // destroy drains the queue before it stops workers
-            // Admit in arrival order while the budget allows.
-            while (!queue.empty() && (int32_t)batch.size() < max_batch &&
-                   reserved + bytes + queue.front().bytes <= budget) {
-                bytes += queue.front().bytes;
-                batch.push_back(queue.front());
-                queue.pop_front();
+            // The oldest request fixes the class; admit requests of that class
+            // in arrival order while the budget allows (a large one alone).
+            const bool large = queue.front().g.m >= kLargeEdges;
+            for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < max_batch;) {
+                if ((it->g.m >= kLargeEdges) != large) {
+                    ++it;
+                    continue;
+                }
+                if (reserved + bytes + it->bytes > budget) break;
+                bytes += it->bytes;
+                batch.push_back(*it);
+                it = queue.erase(it);
+                if (large) break;
             }
             reserved += bytes;
             running += (int64_t)batch.size();
@@ -151,7 +162,7 @@ bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
         E->max_batch = max_batch > 0 ? max_batch : 1024;
         BT_HIP(hipStreamCreateWithFlags(&E->est_stream, hipStreamNonBlocking));
         E->est_ws.coop = false;
-        const int n = slots > 0 ? slots : 2;
+        const int n = slots > 0 ? slots : 1;
         for (int i = 0; i < n; ++i) E->workers.emplace_back(&bt_engine::worker_loop, E, i);
     } catch (const Error &e) {
         set_error(e.msg);

@@ -1,6 +1,8 @@
 // pipeline.h - stages of the hot path and the device views they share.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace bt {
@@ -93,6 +95,11 @@ struct PeelOptions {
 };
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s, const PeelOptions *opt = nullptr);
+
+// Peel of a disjoint union of graphs (edge ranges [off[g], off[g+1])) in
+// which every graph advances at its own level (one cooperative kernel).
+void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
+                const std::vector<int64_t> &off, PeelCounters &pc, Workspace &ws, hipStream_t s);
 
 // Sets the fixed-edge mark in wedge records and link twins (progressive mode).
 void mark_fixed(IndexArrays &ix, const int32_t *fixed, hipStream_t s);
