@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--workload", default="chunglu5m", choices=["chunglu5m", "uniform10k", "hub20m"])
     ap.add_argument("--batch", type=int, default=256,
                     help="graphs of the many-small-graphs pool for the batched-vs-plain line (0: skip)")
+    ap.add_argument("--batch-all", type=int, default=4096,
+                    help="graphs of the pool decomposed as one batch (0: skip)")
     ap.add_argument("--serve", type=float, default=1.0,
                     help="seconds of Poisson arrivals for the served-vs-plain-FIFO line (0: skip)")
     ap.add_argument("--serve-pool", type=int, default=512,
@@ -153,6 +155,9 @@ def main():
     }
     if args.batch > 0:
         out["batched"] = batch_compare(args.batch)
+    if args.batch_all > 0:
+        out["batched_all"] = batch_all(args.batch_all,
+                                       out.get("batched", {}).get("plain_graphs_per_s"))
     if args.serve > 0:
         out["served"] = serve_compare(args.serve, args.serve_pool, args.serve_big)
     if not args.no_cpu:
@@ -187,6 +192,39 @@ def batch_compare(n):
             "plain_edges_per_s": m / t_plain, "batched_edges_per_s": m / t_batch,
             "speedup": t_plain / t_batch, "batched_equals_plain": same,
             "batched_rounds": st["rounds"]}
+
+
+def _pool_graph(i):
+    from paper_2001_06111_amd import synth
+    return synth.batch_graph(i)
+
+
+def batch_all(n, plain_graphs_per_s):
+    """The whole pool batched (graphs generated on host cores in parallel).
+
+    The plain per-graph rate is the one measured on the pool's first graphs
+    (same distribution); the whole pool would take minutes in the plain loop.
+    """
+    import concurrent.futures as cf
+    import torch
+    from paper_2001_06111_amd import binding
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        gs = list(ex.map(_pool_graph, range(n), chunksize=16))
+    dgs = [binding.DeviceGraph.upload(g, "cuda:0") for g in gs]
+    m = sum(g.m for g in gs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st = binding.bt_decompose_batch(dgs, want_sup=False, stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] whole pool of {n}: batched {dt:.3f}s", file=sys.stderr, flush=True)
+    out = {"workload": f"all {n} graphs of the pool", "graphs": n, "edges": m,
+           "batched_graphs_per_s": n / dt, "batched_edges_per_s": m / dt, "seconds": dt,
+           "peel_launches": st["peel_launches"], "rounds_max": st["rounds"]}
+    if plain_graphs_per_s:
+        out["speedup_vs_plain_rate"] = (n / dt) / plain_graphs_per_s
+    return out
 
 
 def serve_compare(seconds, n_small, n_big, rate=200.0):

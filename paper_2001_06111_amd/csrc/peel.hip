@@ -368,10 +368,19 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
     const int cur = R.cur;
     const int32_t thresh = R.thresh;
     if (R.mode == kGather) {
+        // Block-strided, so the block can pool its compaction slots and its
+        // minimum: one atomic per block instead of one per wave on each of
+        // the two contended counters.
+        __shared__ uint32_t s_wcnt[32];
+        __shared__ u64 s_base;
+        __shared__ int32_t s_min;
         const int64_t na = (int64_t)R.na;
+        const int wv = threadIdx.x / kWave, nwv = blockDim.x / kWave;
+        if (threadIdx.x == 0) s_min = INT_MAX;
         int32_t mn = INT_MAX;
-        for (int64_t i0 = wid * kWave; i0 < na; i0 += nwaves * kWave) {
-            const int64_t i = i0 + lane_id();
+        for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < na;
+             i0 += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t i = i0 + threadIdx.x;
             bool take = false, keep = false;
             int32_t e = 0;
             if (i < na) {
@@ -391,12 +400,29 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
             }
             const uint32_t k = take ? link_chunks(lo, hi) : 0u;
             u64 base[3];
-            wave_alloc3(k, &C->nf[q].v, keep ? 1u : 0u, &C->na[cur ^ 1].v, 0u, nullptr, base);
+            wave_alloc3(k, &C->nf[q].v, 0u, nullptr, 0u, nullptr, base);
             put_front(P, q, base[0], e, lo, hi, k, level);
-            if (keep) st(&P.act[cur ^ 1][base[1]], e);
+            const unsigned long long kb = __ballot(keep);
+            if (lane_id() == 0) s_wcnt[wv] = (uint32_t)__popcll(kb);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t t = 0;
+                for (int w = 0; w < nwv; ++w) {
+                    const uint32_t c = s_wcnt[w];
+                    s_wcnt[w] = t;
+                    t += c;
+                }
+                s_base = t ? atomicAdd(&C->na[cur ^ 1].v, (u64)t) : 0;
+            }
+            __syncthreads();
+            if (keep)
+                st(&P.act[cur ^ 1][s_base + s_wcnt[wv] + __popcll(kb & lanemask_lt())], e);
+            __syncthreads();
         }
         mn = wave_min(mn);
-        if (lane_id() == 0 && mn != INT_MAX) atomicMin(&C->gmin[p], mn);
+        if (lane_id() == 0 && mn != INT_MAX) atomicMin(&s_min, mn);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_min != INT_MAX) atomicMin(&C->gmin[p], s_min);
         return;
     }
     const int64_t nf = (int64_t)R.nf;
