@@ -19,6 +19,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
+# Random device-scope int32 atomics per second on one MI355X, measured with a
+# microbenchmark (many waves, one atomic per lane over a 20-160 MB array).
+ATOMIC_PEAK_PER_S = 2.7e10
 
 
 def phi_digest(phi) -> str:
@@ -152,6 +155,11 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes / launches,
                      "avg_launch_ms": st["ms_peel_kernel"] / launches, "launches": launches},
+        # The peel's other ceiling: its support decrements are device-scope atomics.
+        "atomic_throughput": {"decrements_per_s": st["support_updates"] / peel_s if peel_s else 0.0,
+                              "measured_peak_per_s": ATOMIC_PEAK_PER_S,
+                              "frac": (st["support_updates"] / peel_s / ATOMIC_PEAK_PER_S)
+                              if peel_s else 0.0},
     }
     if args.batch > 0:
         out["batched"] = batch_compare(args.batch)

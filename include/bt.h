@@ -169,6 +169,22 @@ bt_status bt_decompose_pc(const bt_csr *g, double tau, int64_t *sup_out, int64_t
                           bt_stats *stats, hipStream_t stream);
 
 /*
+ * Connected components of the k-bitruss H_k (Definition 4: by Definition 5,
+ * the edges with phi_e >= k), the cohesive subgraphs that the applications
+ * of Section I look for.
+ *   phi              device int64[m]: bitruss numbers (from bt_decompose).
+ *   k                any integer; k <= 0 takes every edge.
+ *   comp_out         device int32[m]: the component of edge e, numbered
+ *                    0, 1, ... in order of each component's smallest edge id;
+ *                    -1 where phi_e < k.
+ *   n_components_out host int64 (nullable): the number of components.
+ * The graph is validated (BT_EINVAL if malformed).
+ */
+bt_status bt_bitruss_components(const bt_csr *g, const int64_t *phi, int64_t k,
+                                int32_t *comp_out, int64_t *n_components_out,
+                                hipStream_t stream);
+
+/*
  * Decompose many independent graphs in shared launches.  gs is a HOST
  * array of n_graphs descriptors (device CSRs); sup_out / phi_out are HOST
  * arrays of n_graphs device pointers (sup_out may be NULL, or hold NULLs).

@@ -12,6 +12,8 @@ CPU-baseline leg import this package.  It shares no code with the GPU path
                peel of the baseline algorithm (Algorithm 1).
   index_def.py the maximal priority-obeyed blooms straight from their
                definition (Section IV, Definitions 6-8).
+  query.py     connected components of a k-bitruss (Definitions 4-5) by
+               breadth-first search.
 
 Functions take a graph as (n_upper, n_lower, row_ptr, col): upper-major
 CSR with int64 row pointers and int32 lower ids sorted per row; edge e is

@@ -50,7 +50,7 @@ class bt_index_info(ctypes.Structure):
 
 EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
             "bt_index_free", "bt_decompose", "bt_decompose_pc", "bt_decompose_batch",
-            "bt_release_workspace",
+            "bt_bitruss_components", "bt_release_workspace",
             "bt_last_error", "bt_version"]
 
 _lib = None
@@ -73,13 +73,16 @@ def load():
         L.bt_decompose.argtypes = [ctypes.POINTER(bt_csr), p, p, ctypes.POINTER(bt_stats), p]
         L.bt_decompose_pc.argtypes = [ctypes.POINTER(bt_csr), ctypes.c_double, p, p,
                                       ctypes.POINTER(bt_stats), p]
+        L.bt_bitruss_components.argtypes = [ctypes.POINTER(bt_csr), p, i64, p,
+                                            ctypes.POINTER(i64), p]
         L.bt_decompose_batch.argtypes = [ctypes.POINTER(bt_csr), i32, ctypes.POINTER(p),
                                          ctypes.POINTER(p), ctypes.POINTER(bt_stats), p]
         L.bt_release_workspace.restype = None
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
         for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
-                     "bt_decompose", "bt_decompose_pc", "bt_decompose_batch"):
+                     "bt_decompose", "bt_decompose_pc", "bt_decompose_batch",
+                     "bt_bitruss_components"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -164,6 +167,18 @@ def bt_decompose_pc(g: DeviceGraph, tau: float = 0.1, want_sup: bool = True, sta
     _check(L.bt_decompose_pc(ctypes.byref(c), ctypes.c_double(tau), _ptr(sup), _ptr(phi),
                              ctypes.byref(st) if stats else None, _stream(stream)))
     return sup, phi, (st.as_dict() if stats else None)
+
+
+def bt_bitruss_components(g: DeviceGraph, phi: torch.Tensor, k: int, stream=None):
+    """(int32 component of every edge of the k-bitruss, -1 elsewhere; count)."""
+    L = load()
+    assert phi.dtype == torch.int64 and phi.numel() == g.m
+    comp = torch.empty(g.m, dtype=torch.int32, device=g.col.device)
+    n = ctypes.c_int64(0)
+    c = g.csr()
+    _check(L.bt_bitruss_components(ctypes.byref(c), _ptr(phi), ctypes.c_int64(int(k)), _ptr(comp),
+                                   ctypes.byref(n), _stream(stream)))
+    return comp, int(n.value)
 
 
 def bt_decompose_batch(graphs, want_sup: bool = True, stats: bool = False, stream=None):

@@ -609,6 +609,19 @@ bt_status bt_decompose_pc(const bt_csr *g, double tau, int64_t *sup_out, int64_t
     });
 }
 
+bt_status bt_bitruss_components(const bt_csr *g, const int64_t *phi, int64_t k,
+                                int32_t *comp_out, int64_t *n_components_out,
+                                hipStream_t stream) {
+    return guard([&] {
+        check_graph(g);
+        if (g->m > 0 && (!phi || !comp_out)) throw Error{BT_EINVAL, "phi or comp_out is NULL"};
+        std::lock_guard<std::mutex> lk(lib().mu);
+        validate_graph(*g, lib().ws, stream);
+        const int64_t c = bitruss_components(*g, phi, k, comp_out, lib().ws, stream);
+        if (n_components_out) *n_components_out = c;
+    });
+}
+
 bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const *sup_out,
                              int64_t *const *phi_out, bt_stats *stats, hipStream_t stream) {
     return guard([&] {

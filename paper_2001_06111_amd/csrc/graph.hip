@@ -148,14 +148,9 @@ __global__ void k_rev(const uint64_t *keys, int64_t n2, int nb, const int64_t *o
 
 }  // namespace
 
-void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
+void validate_graph(const bt_csr &g, Workspace &ws, hipStream_t s) {
     const int32_t nu = g.n_upper, nl = g.n_lower;
     const int64_t m = g.m;
-    const int64_t n = (int64_t)nu + nl;
-    r.n_lower = nl;
-    r.n = (int32_t)n;
-    r.m = m;
-
     int64_t *hs = ws.host(4);
     int32_t *flags = ws.get<int32_t>("prep_flags", 4);
     BT_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
@@ -172,6 +167,17 @@ void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
     if (f & kBadCol) throw Error{BT_EINVAL, "a lower id is out of range"};
     if (f & kUnsorted)
         throw Error{BT_EINVAL, "lower ids not strictly increasing within a row (duplicate edge?)"};
+}
+
+void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
+    const int32_t nu = g.n_upper, nl = g.n_lower;
+    const int64_t m = g.m;
+    const int64_t n = (int64_t)nu + nl;
+    r.n_lower = nl;
+    r.n = (int32_t)n;
+    r.m = m;
+
+    validate_graph(g, ws, s);
 
     // Degrees and the priority order.
     int32_t *deg = ws.get<int32_t>("prep_deg", n);

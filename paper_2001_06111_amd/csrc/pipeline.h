@@ -62,6 +62,15 @@ struct IndexArrays {
     int64_t *butterflies = nullptr;  // device scalar
 };
 
+// Checks the CSR on the device (BT_EINVAL with the reason if malformed).
+void validate_graph(const bt_csr &g, Workspace &ws, hipStream_t s);
+
+// Connected components of the k-bitruss (edges with phi >= k): comp[e] is
+// the component of e numbered by smallest edge id, or -1.  Returns their
+// number.  The graph must be valid.
+int64_t bitruss_components(const bt_csr &g, const int64_t *phi, int64_t k, int32_t *comp,
+                           Workspace &ws, hipStream_t s);
+
 // Validates the CSR and builds the rank-space adjacency in `ws`.
 // Throws Error{BT_EINVAL} for malformed input.
 void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s);

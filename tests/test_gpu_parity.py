@@ -186,6 +186,23 @@ def test_engine_alone_equals_mix():
         assert np.array_equal(mix[i][2].cpu().numpy(), ophi)
 
 
+def test_engine_size_classes():
+    """A large request (2^19+ edges) runs alone while small ones are batched past
+    it; every result still equals the plain decomposition."""
+    big = synth.scaled_chunglu(600_000, seed=6)
+    assert big.m >= 1 << 19
+    gs = [synth.batch_graph(i) for i in range(3)] + [big] + [synth.batch_graph(i)
+                                                           for i in range(3, 9)]
+    mix, done, stats = _run_engine(gs, slots=1, stagger=0.001)
+    assert sorted(i for i, _ in done) == list(range(len(gs)))
+    assert stats["batches"] >= 2  # the large request never shares a batch
+    for i, g in enumerate(gs):
+        s, sup, phi = mix[i]
+        assert s == binding.BT_OK
+        ssup, sphi, _ = binding.bt_decompose(upload(g))
+        assert torch.equal(sphi, phi) and torch.equal(ssup, sup)
+
+
 def test_engine_rejects_and_isolates():
     eng = binding.BtEngine(hbm_budget=1 << 20, slots=1)
     g = synth.scaled_chunglu(200_000, seed=2)

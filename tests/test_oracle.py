@@ -265,3 +265,75 @@ def test_index_definition_invariants():
             got = index_def.blooms_at(x, g.n_upper, g.n_lower, g.row_ptr, g.col, key, nbr)
             assert [(a, z) for a, z, _ in got] == [(a, z) for a, z, _ in want]
             assert [len(ys) for _, _, ys in got] == [len(w) for _, _, w in want]
+
+
+# --- k-bitruss components (oracle/query.py) ------------------------------------
+
+def _union_of(parts):
+    """Disjoint union of graphs given as (n_upper, n_lower, edge list) triples."""
+    from paper_2001_06111_amd import synth as _s
+    edges, nu, nl = [], 0, 0
+    for a, b, es in parts:
+        edges += [(u + nu, v + nl) for u, v in es]
+        nu += a
+        nl += b
+    return _s.from_edges(nu, nl, edges)
+
+
+def test_components_of_disjoint_bicliques_closed_form():
+    """K_{3,3} (phi 4 on every edge), K_{2,4} (phi 3), a 5-star (phi 0): H_k has one
+    component per part whose closed-form (a-1)(b-1) reaches k."""
+    from oracle.query import bitruss_components
+    parts = [(3, 3, [(u, v) for u in range(3) for v in range(3)]),
+             (2, 4, [(u, v) for u in range(2) for v in range(4)]),
+             (1, 5, [(0, v) for v in range(5)])]
+    g = _union_of(parts)
+    phi = np.array([4] * 9 + [3] * 8 + [0] * 5)
+    for k, want in [(0, 3), (1, 2), (3, 2), (4, 1), (5, 0)]:
+        comp, c = bitruss_components(g.n_upper, g.n_lower, g.row_ptr, g.col, phi, k)
+        assert c == want
+        assert np.all((comp >= 0) == (phi >= k))
+    comp, c = bitruss_components(g.n_upper, g.n_lower, g.row_ptr, g.col, phi, 1)
+    assert list(comp) == [0] * 9 + [1] * 8 + [-1] * 5  # numbered by smallest edge id
+
+
+def test_components_match_library_routine():
+    """On random graphs and thresholds, the partition equals scipy's connected
+    components of the edge-induced subgraph."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    from oracle.query import bitruss_components
+    rng = np.random.default_rng(5)
+    for t in range(6):
+        g = graphs.random_dense(int(rng.integers(5, 30)), int(rng.integers(5, 30)), 0.15, 40 + t)
+        phi = rng.integers(0, 4, size=g.m)
+        k = int(rng.integers(0, 4))
+        comp, c = bitruss_components(g.n_upper, g.n_lower, g.row_ptr, g.col, phi, k)
+        u, v = g.edges()
+        sel = phi >= k
+        n = g.n_upper + g.n_lower
+        a = sp.coo_matrix((np.ones(sel.sum()), (g.n_lower + u[sel], v[sel])), shape=(n, n))
+        _, lab = connected_components(a, directed=False)
+        ids = np.nonzero(sel)[0]
+        # same partition of the selected edges
+        pairs = {}
+        for e in ids:
+            pairs.setdefault(lab[v[e]], set()).add(comp[e])
+        assert all(len(x) == 1 for x in pairs.values())
+        assert len(pairs) == c and len(set(comp[ids])) == c
+        firsts = [int(ids[comp[ids] == i][0]) for i in range(c)]
+        assert firsts == sorted(firsts)
+
+
+def test_components_of_the_worked_example():
+    """Section II's example: H_2 (the six edges of bitruss number 2) and H_1 are
+    each one connected group."""
+    from oracle.query import bitruss_components
+    for grey in (True, False):
+        g, nm, fx = graphs.worked_example(grey)
+        phi = np.zeros(g.m, dtype=np.int64)  # grey edges: 0
+        for i in range(9):
+            phi[nm[f"e{i}"]] = fx["phi"][f"e{i}"]
+        for k in (1, 2):
+            _, c = bitruss_components(g.n_upper, g.n_lower, g.row_ptr, g.col, phi, k)
+            assert c == 1
