@@ -149,7 +149,8 @@ def main():
         "phases_ms": {k: round(st[k], 3) for k in ("ms_prepare", "ms_count", "ms_link", "ms_peel")},
         "counters": {k: st[k] for k in ("butterflies", "wedges_po", "blooms", "bloom_wedges",
                                         "levels", "rounds", "max_phi", "support_updates",
-                                        "bloom_visits", "index_bytes")},
+                                        "bloom_visits", "index_bytes",
+                                        "support_updates_unbatched")},
         "roofline": {"kernel": "k_peel_persistent (bloom peel, all rounds)", "bound": "hbm",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,

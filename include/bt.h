@@ -87,6 +87,10 @@ typedef struct bt_stats {
     float ms_peel_kernel;     /* device time of the peel kernels alone (HIP events) */
     int32_t peel_launches;    /* peel kernel (or round-graph) launches */
     int32_t passes;           /* subgraph passes (1, or BiT-PC's thresholds) */
+    int64_t support_updates_unbatched; /* the plain peel's decrements had each
+                                 survivor taken one unit per removed wedge (no
+                                 batch bloom processing, Section V-B); 0 where
+                                 not counted */
 } bt_stats;
 
 /* Opaque device-resident BE-Index. */

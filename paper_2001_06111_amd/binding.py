@@ -37,7 +37,8 @@ class bt_stats(ctypes.Structure):
         "rounds", "max_phi", "support_updates", "bloom_visits")] + [
         (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel",
                                       "ms_peel_kernel")] + [
-        ("peel_launches", ctypes.c_int32), ("passes", ctypes.c_int32)]
+        ("peel_launches", ctypes.c_int32), ("passes", ctypes.c_int32),
+        ("support_updates_unbatched", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -151,6 +151,7 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->ms_peel_kernel = (float)pc.kernel_ms;
     stats->peel_launches = (int32_t)pc.launches;
     stats->passes = 1;
+    stats->support_updates_unbatched = pc.updates_unbatched;
 }
 
 }  // namespace
@@ -376,6 +377,7 @@ void add_stats(bt_stats &t, const bt_stats &s) {
     t.ms_peel_kernel += s.ms_peel_kernel;
     t.peel_launches += s.peel_launches;
     t.passes = std::max(t.passes, s.passes);
+    t.support_updates_unbatched += s.support_updates_unbatched;
 }
 
 // Graphs [a, b) as one union; splits the range if the union is too large.

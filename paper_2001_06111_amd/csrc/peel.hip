@@ -97,6 +97,7 @@ struct PeelCtl {
     Counter na[2];      // active-set entries by buffer
     Counter updates;
     Counter bloom_visits;
+    Counter unbatched;  // extra decrements if survivors took one per kill (no bloom batching)
     // Round state, indexed by round parity.  Round r's entry is derived
     // from round r - 1's final counters (every block computes the same
     // values; block 0 stores them for round r + 1).
@@ -489,7 +490,7 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
 // round; across the threshold, adds it to the active set.
 __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Round &R,
                                              int64_t wid, int64_t nwaves, bool lead, u64 &upd,
-                                             u64 &visits) {
+                                             u64 &visits, u64 &unb) {
     PeelCtl *C = P.ctl;
     const int q = p ^ 1;
     const int32_t level = R.level;
@@ -558,6 +559,9 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         if (a1) st(&P.act[cur][base[1]], ea);
         if (a2) st(&P.act[cur][base[1] + (a1 ? 1 : 0)], eb);
         upd += (da ? 1 : 0) + (db ? 1 : 0);
+        // Without batch bloom processing each of the C kills would lower each
+        // survivor by one: C unit updates where one update of C is issued.
+        unb += (u64)((da ? c - 1 : 0) + (db ? c - 1 : 0));
         if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
         if (last) {
             st(&P.bk[b], kn);
@@ -571,12 +575,14 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
 }
 
 // Adds per-lane statistics to the control block (one atomic per wave).
-__device__ __forceinline__ void flush_stats(PeelCtl *C, u64 upd, u64 visits) {
+__device__ __forceinline__ void flush_stats(PeelCtl *C, u64 upd, u64 visits, u64 unb = 0) {
     upd = wave_sum(upd);
     visits = wave_sum(visits);
+    unb = wave_sum(unb);
     if (lane_id() == 0) {
         if (upd) atomicAdd(&C->updates.v, upd);
         if (visits) atomicAdd(&C->bloom_visits.v, visits);
+        if (unb) atomicAdd(&C->unbatched.v, unb);
     }
 }
 
@@ -620,11 +626,11 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
     __syncthreads();
     if (!s_ok) return;
     const Round R = sR;
-    u64 upd = 0, visits = 0;
+    u64 upd = 0, visits = 0, unb = 0;
     phase_b_work(P, p, R, (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x,
                  (int64_t)gridDim.x * kWavesPerBlock, blockIdx.x == 0 && threadIdx.x == 0, upd,
-                 visits);
-    flush_stats(C, upd, visits);
+                 visits, unb);
+    flush_stats(C, upd, visits, unb);
 }
 
 // --- persistent cooperative kernel: rounds separated by grid barriers ---
@@ -695,7 +701,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
     int p = 0;
     u64 t[5] = {0, 0, 0, 0, 0}, acc[6] = {0, 0, 0, 0, 0, 0};
-    u64 upd = 0, visits = 0;
+    u64 upd = 0, visits = 0, unb = 0;
     LeadStats L{};
     if (lead) L.load(C);
     if (threadIdx.x == 0) s_ok = decide_round(C, p, lead, sR, L, P.prof);
@@ -715,7 +721,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         if (!s_ok) break;
         R.ntc = sR.ntc;
         if (prof && lead) t[2] = wall_clock64();
-        phase_b_work(P, p, R, wid, nwaves, lead, upd, visits);
+        phase_b_work(P, p, R, wid, nwaves, lead, upd, visits, unb);
         if (prof && lead) t[3] = wall_clock64();
         drain_memory();
         __syncthreads();
@@ -733,7 +739,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         }
         p ^= 1;
     }
-    flush_stats(C, upd, visits);
+    flush_stats(C, upd, visits, unb);
     if (lead) {
         L.store(C);
         st(&C->pad, p);
@@ -1445,6 +1451,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     pc.max_phi = hc->max_level;
     pc.updates = (int64_t)hc->updates.v;
     pc.bloom_visits = (int64_t)hc->bloom_visits.v;
+    pc.updates_unbatched = pc.updates + (int64_t)hc->unbatched.v;
     if (std::getenv("BT_PEEL_PROFILE"))
         std::fprintf(stderr, "[peel] rounds %llu  block0 us: phaseA %.0f bar1 %.0f phaseB %.0f bar2 %.0f; gather rounds %llu phaseA+bar1 %.0f\n",
                      hc->rounds, hc->prof[0] / 100.0, hc->prof[1] / 100.0, hc->prof[2] / 100.0,

@@ -92,6 +92,7 @@ void build_index(const RankCSR &r, const TaskLists &t, IndexArrays &ix, Workspac
 // supports, phi_out (int64) the bitruss numbers.
 struct PeelCounters {
     int64_t levels = 0, rounds = 0, max_phi = 0, updates = 0, bloom_visits = 0;
+    int64_t updates_unbatched = 0;  // the same peel without batch bloom processing
     double kernel_ms = 0;  // HIP-event time of the peel kernel launches
     int64_t launches = 0;
 };

@@ -1,4 +1,4 @@
-"""Full-size parity: the 5M-edge Chung-Lu workload against the oracle.
+"""Full-size parity: the 5M-edge Chung-Lu workload and 512 pool graphs against the oracle.
 
 Bitruss numbers and supports are compared bit for bit through SHA-256
 digests of the oracle's outputs (tests/golden/digests.json, written by
@@ -57,3 +57,24 @@ def test_uniform10k_digests():
     sup, phi, st = binding.bt_decompose(binding.DeviceGraph.upload(g), stats=True)
     want = GOLD[g.name]
     assert sha(sup.cpu().numpy()) == want["sup_sha256"] and sha(phi.cpu().numpy()) == want["phi_sha256"]
+
+
+def test_pool512_batched_digests():
+    """The first 512 graphs of the many-small-graphs pool, decomposed as one
+    batched call (each graph at its own level): the concatenated supports and
+    bitruss numbers equal the oracle's, bit for bit."""
+    want = GOLD["pool:512"]
+    assert want["generator_version"] == synth.GENERATOR_VERSION
+    gs = [synth.batch_graph(i) for i in range(512)]
+    dgs = [binding.DeviceGraph.upload(g) for g in gs]
+    sups, phis, st = binding.bt_decompose_batch(dgs, stats=True)
+    torch.cuda.synchronize()
+    hs, hp = hashlib.sha256(), hashlib.sha256()
+    for s, p in zip(sups, phis):
+        hs.update(np.ascontiguousarray(s.cpu().numpy(), dtype="<i8").tobytes())
+        hp.update(np.ascontiguousarray(p.cpu().numpy(), dtype="<i8").tobytes())
+    assert st["butterflies"] == want["butterflies"]
+    assert hs.hexdigest() == want["sup_sha256"]
+    assert hp.hexdigest() == want["phi_sha256"]
+    for i, g in enumerate(want["per_graph"]):
+        assert sha(phis[i].cpu().numpy()) == g["phi_sha256"]
