@@ -687,11 +687,195 @@ __device__ bool grid_arrive_wait(GridBar *B, u64 &k) {
     return ok;
 }
 
+// Rebuild of the active set inside the persistent kernel, when it has run
+// dry: the remaining edges (phi < 0) are compacted from one list into the
+// other while their minimum support mn is found; a log2 histogram of
+// support - mn picks the threshold T that puts a few percent of them (at
+// least 65,536) in the active set; the edges below T are gathered into
+// active buffer 0; and the round state is set as if the previous round had
+// been a gather that saw minimum support mn.  Counters are pooled per
+// workgroup.  Every workgroup derives T from the same histogram.
+struct RefillState {
+    Counter count;     // entries of the list being written
+    int32_t min;       // minimum remaining support (INT_MAX: none)
+    int32_t cur;       // list holding the remaining edges; -1: all edges, in id order
+    int64_t n_all;     // its length
+    int32_t done;      // set when no edge remains
+    int32_t pad;
+    u64 hist[33];
+};
+
+struct RefillArgs {
+    RefillState *rs;
+    int32_t *list[2];
+    int32_t min_level;  // progressive mode: the first level is at least this
+};
+
+// Reserves `keep` slots of *ctr for each thread, one atomic per workgroup.
+// All threads of the workgroup must call.
+__device__ __forceinline__ u64 block_alloc(bool keep, u64 *ctr) {
+    __shared__ uint32_t s_w[32];
+    __shared__ u64 s_b;
+    const int wv = threadIdx.x / kWave, nwv = blockDim.x / kWave;
+    const unsigned long long kb = __ballot(keep);
+    if (lane_id() == 0) s_w[wv] = (uint32_t)__popcll(kb);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < nwv; ++w) {
+            const uint32_t c = s_w[w];
+            s_w[w] = t;
+            t += c;
+        }
+        s_b = t ? atomicAdd(ctr, (u64)t) : 0;
+    }
+    __syncthreads();
+    const u64 slot = s_b + s_w[wv] + __popcll(kb & lanemask_lt());
+    __syncthreads();
+    return slot;
+}
+
+// Returns the number of remaining edges (0: the peel is complete); *ok is
+// cleared if a barrier gave up.  All threads of the grid must call.
+__device__ int64_t grid_refill(const PeelArgs &P, const RefillArgs &RA, GridBar *B,
+                               u64 &gen_local, bool lead, int &ok) {
+    __shared__ int64_t s_n;
+    __shared__ int32_t s_cur, s_mn, s_T;
+    __shared__ int s_ok2;
+    __shared__ unsigned s_hist[33];
+    PeelCtl *C = P.ctl;
+    RefillState *RS = RA.rs;
+    if (threadIdx.x == 0) {
+        s_cur = ld(&RS->cur);
+        s_n = ld(&RS->n_all);
+    }
+    if (lead) {
+        st(&C->na[0].v, (u64)0);
+        st(&C->na[1].v, (u64)0);
+    }
+    __syncthreads();
+    const int32_t cur = s_cur, nxt = cur < 0 ? 0 : cur ^ 1;
+    const int64_t n0 = s_n;
+    int32_t mn = INT_MAX;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n0; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        int32_t e = 0;
+        bool keep = false;
+        if (i < n0) {
+            e = cur < 0 ? (int32_t)i : ld(&RA.list[cur][i]);
+            keep = ld(&P.phi[e]) < 0;
+            if (keep) mn = min(mn, ld(&P.sup[e]));
+        }
+        const u64 slot = block_alloc(keep, &RS->count.v);
+        if (keep) st(&RA.list[nxt][slot], e);
+    }
+    mn = wave_min(mn);
+    if (lane_id() == 0 && mn != INT_MAX) atomicMin(&RS->min, mn);
+    drain_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_ok2 = grid_arrive_wait(B, gen_local);
+        s_n = (int64_t)ld(&RS->count.v);
+        s_mn = ld(&RS->min);
+    }
+    if (threadIdx.x < 33) s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    if (!s_ok2) {
+        ok = 0;
+        return 0;
+    }
+    const int64_t n = s_n;
+    if (n == 0) {
+        if (lead) st(&RS->done, 1);
+        return 0;
+    }
+    const int32_t m0 = s_mn;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t d = (uint32_t)(ld(&P.sup[ld(&RA.list[nxt][i])]) - m0) + 1u;
+        atomicAdd(&s_hist[31 - __clz(d)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 33 && s_hist[threadIdx.x]) atomicAdd(&RS->hist[threadIdx.x], (u64)s_hist[threadIdx.x]);
+    drain_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_ok2 = grid_arrive_wait(B, gen_local);
+        // Threshold: the set holds at least max(65536, n / 32) edges, and every
+        // edge at or below the first level.
+        const int32_t lvl = max(m0, RA.min_level);
+        const int64_t target = max((int64_t)65536, n / 32);
+        int64_t T = INT_MAX, acc = 0;
+        for (int b = 0; b < 33; ++b) {
+            acc += (int64_t)ld(&RS->hist[b]);
+            if (acc >= target) {
+                T = min((int64_t)m0 + (int64_t(2) << b) - 1, (int64_t)INT_MAX);
+                break;
+            }
+        }
+        T = max(T, min((int64_t)lvl + 1, (int64_t)INT_MAX));
+        s_T = (int32_t)T;
+        s_mn = lvl;
+    }
+    __syncthreads();
+    if (!s_ok2) {
+        ok = 0;
+        return 0;
+    }
+    const int32_t T = s_T;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        int32_t e = 0;
+        bool take = false;
+        if (i < n) {
+            e = ld(&RA.list[nxt][i]);
+            take = ld(&P.sup[e]) < T;
+        }
+        const u64 slot = block_alloc(take, &C->na[0].v);
+        if (take) st(&P.act[0][slot], e);
+    }
+    drain_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) s_ok2 = grid_arrive_wait(B, gen_local);
+    __syncthreads();
+    if (!s_ok2) {
+        ok = 0;
+        return 0;
+    }
+    if (lead) {
+        // As if the previous round (parity 1) had been a gather that found no
+        // frontier and saw minimum support s_mn in buffer 0.
+        for (int k = 0; k < 2; ++k) {
+            st(&C->nf[k].v, (u64)0);
+            st(&C->ntc[k].v, (u64)0);
+        }
+        st(&C->mode[1], (int32_t)kGather);
+        st(&C->cur[1], 1);
+        st(&C->gmin[1], s_mn);
+        st(&C->gmin[0], (int32_t)INT_MAX);
+        st(&C->stall, 0);
+        st(&C->thresh, T);
+        // The next refill starts from this list.
+        st(&RS->cur, nxt);
+        st(&RS->n_all, n);
+        st(&RS->count.v, (u64)0);
+        st(&RS->min, (int32_t)INT_MAX);
+        for (int b = 0; b < 33; ++b) st(&RS->hist[b], (u64)0);
+    }
+    drain_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) s_ok2 = grid_arrive_wait(B, gen_local);
+    __syncthreads();
+    if (!s_ok2) ok = 0;
+    return s_ok2 ? n : 0;
+}
+
 __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar *B,
-                                                             int64_t max_rounds, int prof) {
+                                                             int64_t max_rounds, int prof,
+                                                             RefillArgs RA) {
     PeelCtl *C = P.ctl;
     __shared__ Round sR;
-    __shared__ int s_ok;
+    __shared__ int s_ok, s_fail;
     u64 gen_local = 0;  // barriers passed (the host clears the barrier per launch)
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     // Wave ids run across blocks first: a small round spreads its work items
@@ -704,9 +888,21 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     u64 upd = 0, visits = 0, unb = 0;
     LeadStats L{};
     if (lead) L.load(C);
+    if (threadIdx.x == 0) s_fail = 0;
+    __syncthreads();
+    int64_t r = 0;
+    while (r < max_rounds) {
+    // The active set is (re)built here whenever it runs dry; the peel ends
+    // when no edge remains.
+    int ok = 1;
+    if (grid_refill(P, RA, B, gen_local, lead, ok) == 0) {
+        if (!ok && threadIdx.x == 0) s_fail = 1;
+        break;
+    }
+    p = 0;
     if (threadIdx.x == 0) s_ok = decide_round(C, p, lead, sR, L, P.prof);
     __syncthreads();
-    for (int64_t r = 0; r < max_rounds && s_ok; ++r) {
+    for (; r < max_rounds && s_ok; ++r) {
         if (prof && lead) t[0] = wall_clock64();
         Round R = sR;
         phase_a_work(P, p, R, wid, nwaves, upd);
@@ -715,6 +911,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         __syncthreads();
         if (threadIdx.x == 0) {
             s_ok = grid_arrive_wait(B, gen_local);
+            if (!s_ok) s_fail = 1;
             sR.ntc = ld(&C->ntc[p].v);
         }
         __syncthreads();
@@ -726,7 +923,9 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         drain_memory();
         __syncthreads();
         if (threadIdx.x == 0) {
-            s_ok = grid_arrive_wait(B, gen_local) && decide_round(C, p ^ 1, lead, sR, L, P.prof);
+            const bool bar = grid_arrive_wait(B, gen_local);
+            if (!bar) s_fail = 1;
+            s_ok = bar && decide_round(C, p ^ 1, lead, sR, L, P.prof);
         }
         __syncthreads();
         if (prof && lead) {
@@ -738,6 +937,8 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
             }
         }
         p ^= 1;
+    }
+    if (s_fail) break;
     }
     flush_stats(C, upd, visits, unb);
     if (lead) {
@@ -1313,7 +1514,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     u64 *hr = reinterpret_cast<u64 *>(hc + 1);
     // BT_PEEL_MODE=graph replays captured two-kernel rounds instead of the
     // persistent kernel; BT_PEEL_GRAPH=0 launches those rounds directly.
-    // BT_PEEL_VERBOSE=1 prints one line per persistent launch (long peels).
+    // BT_PEEL_VERBOSE=1 prints the time of the persistent launch.
     const bool verbose = std::getenv("BT_PEEL_VERBOSE") != nullptr;
     const char *mv = std::getenv("BT_PEEL_MODE");
     const bool persistent = ws.coop && !(mv && std::strcmp(mv, "graph") == 0);
@@ -1344,6 +1545,36 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             (void)hipEventDestroy(b);
         }
     } ev_free{ev0, ev1};
+    if (persistent) {
+        // One launch: the kernel rebuilds the active set itself whenever it
+        // runs dry and stops when no edge remains.
+        RefillState rs0{};
+        rs0.min = INT_MAX;
+        rs0.cur = -1;  // all edges, in id order
+        rs0.n_all = m;
+        RefillState *drs = ws.get<RefillState>("peel_refill_state", 1);
+        BT_HIP(hipMemcpyAsync(drs, &rs0, sizeof rs0, hipMemcpyHostToDevice, s));
+        RefillArgs RA{drs, {glist[0], glist[1]}, min_level};
+        int64_t max_rounds = 4 * m + 64;
+        int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
+        void *args[] = {&P, &bar, &max_rounds, &prof, &RA};
+        BT_HIP(hipEventRecord(ev0, s));
+        BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
+                                          dim3(kPBlock), args, 0, s));
+        BT_HIP(hipEventRecord(ev1, s));
+        int32_t fail = 0;
+        BT_HIP(hipMemcpyAsync(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost, s));
+        BT_HIP(hipMemcpyAsync(&rs0, drs, sizeof rs0, hipMemcpyDeviceToHost, s));
+        BT_HIP(hipStreamSynchronize(s));
+        float t = 0.f;
+        BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
+        pc.kernel_ms += t;
+        pc.launches += 1;
+        if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
+        if (!rs0.done) throw Error{BT_EDEVICE, "peel stopped early"};
+        if (verbose)
+            std::fprintf(stderr, "[peel] one launch: %.1f ms\n", (double)t);
+    } else {
     int64_t n_all = m;
     int cur = -1;  // -1: all edges, in id order
     int chunk = 4;
@@ -1408,14 +1639,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             need_refill = false;
         }
         BT_HIP(hipEventRecord(ev0, s));
-        if (persistent) {
-            int64_t max_rounds = 4 * m + 64;
-            int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
-            void *args[] = {&P, &bar, &max_rounds, &prof};
-            BT_HIP(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
-            BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
-                                              dim3(kPBlock), args, 0, s));
-        } else if (use_graph) {
+        if (use_graph) {
             BT_HIP(hipGraphLaunch(chunk_graph(P, chunk, ws), s));
         } else {
             for (int rr = 0; rr < chunk; ++rr) launch_round(P, rr & 1, s);
@@ -1430,19 +1654,10 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             pc.kernel_ms += t;
             pc.launches += 1;
         }
-        if (persistent) {
-            int32_t fail = 0;
-            BT_HIP(hipMemcpy(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost));
-            if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
-            if (!hc->stall) throw Error{BT_EDEVICE, "peel stopped early"};
-        }
         if (hc->stall) need_refill = true;
-        if (verbose && persistent)
-            std::fprintf(stderr, "[peel] launch %lld: %lld edges remained, level %d, rounds %llu, %.1f ms\n",
-                         (long long)pc.launches, (long long)n_all, hc->max_level, hc->rounds,
-                         (double)pc.kernel_ms);
         chunk = std::min(chunk * 2, 64);
         if (guard > 4 * m + 64) throw Error{BT_EDEVICE, "peel made no progress"};
+    }
     }
     BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
