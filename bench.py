@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=512,
                     help="small graphs in the request pool (of the 4096)")
     ap.add_argument("--serve-big", type=int, default=4, help="2M-edge graphs in the request pool")
+    ap.add_argument("--ablation", type=int, default=1,
+                    help="also peel once without batch bloom processing (BiT-BU+); 0 = skip")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 256 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -162,6 +164,8 @@ def main():
                               "frac": (st["support_updates"] / peel_s / ATOMIC_PEAK_PER_S)
                               if peel_s else 0.0},
     }
+    if args.ablation:
+        out["ablation"] = ablation(dg, phi_h, st)
     if args.batch > 0:
         out["batched"] = batch_compare(args.batch)
     if args.batch_all > 0:
@@ -173,6 +177,24 @@ def main():
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_frac)
     print(json.dumps(out), flush=True)
+
+
+def ablation(dg, phi_ref, st_bloom):
+    """One decompose of the same graph by BiT-BU+ (batch edge processing
+    only): its peel time and support updates against BiT-BU++'s."""
+    from paper_2001_06111_amd import binding
+    print("[bench] ablation: peel without batch bloom processing", file=sys.stderr, flush=True)
+    _, phi_e, st_e = binding.bt_decompose_variant(dg, binding.BT_PEEL_BATCH_EDGE, want_sup=False,
+                                                  stats=True)
+    same = bool((phi_e.cpu().numpy() == phi_ref).all())
+    return {"variant": "BiT-BU+ (batch edge processing only)",
+            "same_phi": same,
+            "peel_ms": round(st_e["ms_peel_kernel"], 3),
+            "peel_ms_batched": round(st_bloom["ms_peel_kernel"], 3),
+            "support_updates": st_e["support_updates"],
+            "support_updates_batched": st_bloom["support_updates"],
+            "time_ratio": st_e["ms_peel_kernel"] / st_bloom["ms_peel_kernel"]
+            if st_bloom["ms_peel_kernel"] else None}
 
 
 def batch_compare(n):

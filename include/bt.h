@@ -154,6 +154,30 @@ void bt_index_free(bt_index *idx);
 bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
                        bt_stats *stats, hipStream_t stream);
 
+/* Peel variants, for measuring what batch bloom processing saves
+ * (Section V-B and the evaluation of the batch optimisations). */
+typedef enum bt_peel_variant {
+    /* BiT-BU++ (Algorithm 5): batch edge and batch bloom processing; a
+     * survivor of a bloom that lost C wedges this round takes one decrement
+     * of C.  This is bt_decompose. */
+    BT_PEEL_BATCH_BLOOM = 0,
+    /* BiT-BU+: batch edge processing only; a survivor takes C decrements of
+     * one, as when each removed edge updates its blooms on its own
+     * (Algorithm 4's removal step).  The bloom's wedges are still read once
+     * per round. */
+    BT_PEEL_BATCH_EDGE = 1
+} bt_peel_variant;
+
+/*
+ * bt_decompose with a chosen peel variant (bt_peel_variant; else
+ * BT_EINVAL).  Results are identical for every variant; stats
+ * support_updates counts the decrements the variant issued (for
+ * BT_PEEL_BATCH_EDGE it equals BT_PEEL_BATCH_BLOOM's
+ * support_updates_unbatched).  Arguments as for bt_decompose.
+ */
+bt_status bt_decompose_variant(const bt_csr *g, int32_t variant, int64_t *sup_out,
+                               int64_t *phi_out, bt_stats *stats, hipStream_t stream);
+
 /*
  * Bitruss numbers by progressive compression, BiT-PC (Section V-C,
  * Algorithms 6-7): for thresholds eps = k_max, k_max - alpha, ..., 0 with

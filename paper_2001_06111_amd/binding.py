@@ -50,7 +50,8 @@ class bt_index_info(ctypes.Structure):
 
 
 EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
-            "bt_index_free", "bt_decompose", "bt_decompose_pc", "bt_decompose_batch",
+            "bt_index_free", "bt_decompose", "bt_decompose_variant", "bt_decompose_pc",
+            "bt_decompose_batch",
             "bt_bitruss_components", "bt_release_workspace",
             "bt_last_error", "bt_version"]
 
@@ -72,6 +73,8 @@ def load():
         L.bt_index_free.argtypes = [p]
         L.bt_index_free.restype = None
         L.bt_decompose.argtypes = [ctypes.POINTER(bt_csr), p, p, ctypes.POINTER(bt_stats), p]
+        L.bt_decompose_variant.argtypes = [ctypes.POINTER(bt_csr), i32, p, p,
+                                           ctypes.POINTER(bt_stats), p]
         L.bt_decompose_pc.argtypes = [ctypes.POINTER(bt_csr), ctypes.c_double, p, p,
                                       ctypes.POINTER(bt_stats), p]
         L.bt_bitruss_components.argtypes = [ctypes.POINTER(bt_csr), p, i64, p,
@@ -82,7 +85,8 @@ def load():
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
         for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
-                     "bt_decompose", "bt_decompose_pc", "bt_decompose_batch",
+                     "bt_decompose", "bt_decompose_variant", "bt_decompose_pc",
+                     "bt_decompose_batch",
                      "bt_bitruss_components"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -151,6 +155,25 @@ def bt_decompose(g: DeviceGraph, want_sup: bool = True, stats: bool = False, str
     c = g.csr()
     _check(L.bt_decompose(ctypes.byref(c), _ptr(sup), _ptr(phi),
                           ctypes.byref(st) if stats else None, _stream(stream)))
+    return sup, phi, (st.as_dict() if stats else None)
+
+
+BT_PEEL_BATCH_BLOOM, BT_PEEL_BATCH_EDGE = 0, 1
+
+
+def bt_decompose_variant(g: DeviceGraph, variant: int, want_sup: bool = True,
+                         stats: bool = False, stream=None):
+    """bt_decompose with a chosen peel variant (BT_PEEL_*): (supports or None,
+    bitruss numbers, stats dict or None)."""
+    L = load()
+    dev = g.col.device
+    phi = torch.empty(g.m, dtype=torch.int64, device=dev)
+    sup = torch.empty(g.m, dtype=torch.int64, device=dev) if want_sup else None
+    st = bt_stats()
+    c = g.csr()
+    _check(L.bt_decompose_variant(ctypes.byref(c), ctypes.c_int32(int(variant)), _ptr(sup),
+                                  _ptr(phi), ctypes.byref(st) if stats else None,
+                                  _stream(stream)))
     return sup, phi, (st.as_dict() if stats else None)
 
 

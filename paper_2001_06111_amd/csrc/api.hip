@@ -157,7 +157,7 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
 }  // namespace
 
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
-                    Workspace &ws, hipStream_t stream) {
+                    Workspace &ws, hipStream_t stream, bool unit_updates) {
     Events ev(stats != nullptr, stream);
     ev.mark(0);
     RankCSR r;
@@ -165,7 +165,9 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
     build_all(g, r, ix, false, nullptr, ws, stream, &ev);
     ev.mark(3);
     PeelCounters pc;
-    peel(r, ix, sup_out, phi_out, pc, ws, stream);
+    PeelOptions o;
+    o.unit_updates = unit_updates;
+    peel(r, ix, sup_out, phi_out, pc, ws, stream, &o);
     ev.mark(4);
     int64_t *hs = ws.host(2);
     BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
@@ -597,6 +599,19 @@ bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out, bt_s
         if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
         std::lock_guard<std::mutex> lk(lib().mu);
         decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream);
+    });
+}
+
+bt_status bt_decompose_variant(const bt_csr *g, int32_t variant, int64_t *sup_out,
+                               int64_t *phi_out, bt_stats *stats, hipStream_t stream) {
+    return guard([&] {
+        check_graph(g);
+        if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
+        if (variant != BT_PEEL_BATCH_BLOOM && variant != BT_PEEL_BATCH_EDGE)
+            throw Error{BT_EINVAL, "unknown peel variant"};
+        std::lock_guard<std::mutex> lk(lib().mu);
+        decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream,
+                       variant == BT_PEEL_BATCH_EDGE);
     });
 }
 

@@ -146,6 +146,7 @@ struct PeelArgs {
     const int64_t *link_off;
     const uint3 *link;  // {wedge, bloom, twin edge}
     int32_t prof;       // count profile statistics
+    int32_t unit;       // ablation without batch bloom processing (BiT-BU+)
     FrontItem *front[2];
     BloomItem *tc[2];
     int32_t *act[2];
@@ -524,10 +525,30 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         const int32_t kn = ld(&P.bk[b]) - c;
         const bool live = inr && kn > 0 && ((word >> (w & 31)) & 1u);
         const bool da = live && !(ra & kFixedBit), db = live && !(rb & kFixedBit);
-        int32_t o1 = 0, o2 = 0;
-        if (live) {
-            if (da) o1 = atomicSub(&P.sup[ea], c);
-            if (db) o2 = atomicSub(&P.sup[eb], c);
+        bool f1 = false, f2 = false, a1 = false, a2 = false;
+        if (live && P.unit) {
+            // Ablation: each of the C[B] kills takes one unit from every
+            // survivor, as removing the edges one at a time would.  Only the
+            // unit decrement from level + 1 (from the threshold) reports the
+            // crossing of the level (of the threshold).
+            for (int32_t t = 0; t < c; ++t) {
+                const int32_t u1 = da ? atomicSub(&P.sup[ea], 1) : 0;
+                const int32_t u2 = db ? atomicSub(&P.sup[eb], 1) : 0;
+                f1 |= da && u1 == level + 1;
+                f2 |= db && u2 == level + 1;
+                a1 |= da && u1 == thresh;
+                a2 |= db && u2 == thresh;
+            }
+        } else {
+            int32_t o1 = 0, o2 = 0;
+            if (live) {
+                if (da) o1 = atomicSub(&P.sup[ea], c);
+                if (db) o2 = atomicSub(&P.sup[eb], c);
+            }
+            f1 = da && o1 > level && o1 - c <= level;
+            f2 = db && o2 > level && o2 - c <= level;
+            a1 = da && o1 >= thresh && o1 - c < thresh;
+            a2 = db && o2 >= thresh && o2 - c < thresh;
         }
         // The chunk counts itself done only once its reads of C[B] and k[B]
         // have returned (the condition uses them), so the last chunk's
@@ -535,10 +556,6 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         bool last = false;
         if (lane_id() == 0 && kn != INT_MIN)
             last = it.nch == 1 || atomicAdd(&P.bdone[b], 1) == it.nch - 1;
-        const bool f1 = da && o1 > level && o1 - c <= level;
-        const bool f2 = db && o2 > level && o2 - c <= level;
-        const bool a1 = da && o1 >= thresh && o1 - c < thresh;
-        const bool a2 = db && o2 >= thresh && o2 - c < thresh;
         uint32_t lo1 = 0, hi1 = 0, lo2 = 0, hi2 = 0;
         if (f1) {
             lo1 = (uint32_t)P.link_off[ea];
@@ -558,10 +575,11 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         put_front(P, q, base[0] + k1, eb, lo2, hi2, k2, level);
         if (a1) st(&P.act[cur][base[1]], ea);
         if (a2) st(&P.act[cur][base[1] + (a1 ? 1 : 0)], eb);
-        upd += (da ? 1 : 0) + (db ? 1 : 0);
+        const int32_t per = P.unit ? c : 1;  // decrements per survivor edge
+        upd += (u64)((da ? per : 0) + (db ? per : 0));
         // Without batch bloom processing each of the C kills would lower each
         // survivor by one: C unit updates where one update of C is issued.
-        unb += (u64)((da ? c - 1 : 0) + (db ? c - 1 : 0));
+        if (!P.unit) unb += (u64)((da ? c - 1 : 0) + (db ? c - 1 : 0));
         if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
         if (last) {
             st(&P.bk[b], kn);
@@ -884,10 +902,15 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     const int64_t wid = (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
     const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
     int p = 0;
-    u64 t[5] = {0, 0, 0, 0, 0}, acc[6] = {0, 0, 0, 0, 0, 0};
+    // The lead's clocks and counters live in LDS, not in every lane's
+    // registers (which would push the kernel past 128 VGPRs into spills).
+    __shared__ u64 t[5], acc[6];
+    __shared__ LeadStats L;
     u64 upd = 0, visits = 0, unb = 0;
-    LeadStats L{};
-    if (lead) L.load(C);
+    if (lead) {
+        L.load(C);
+        for (int k = 0; k < 6; ++k) acc[k] = 0;
+    }
     if (threadIdx.x == 0) s_fail = 0;
     __syncthreads();
     int64_t r = 0;
@@ -1466,6 +1489,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s, const PeelOptions *opt) {
     const int32_t *fixed = opt ? opt->fixed : nullptr;
     const int32_t min_level = opt ? opt->min_level : 0;
+    const int32_t unit = opt && opt->unit_updates ? 1 : 0;
     const int64_t m = r.m;
     if (m == 0) return;
     if (2 * ix.n_w >= (int64_t)UINT32_MAX)
@@ -1496,6 +1520,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     P.act[1] = ws.get<int32_t>("peel_act1", m);
     P.ctl = ws.get<PeelCtl>("peel_ctl", 1);
     P.prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
+    P.unit = unit;
     int32_t *glist[2] = {ws.get<int32_t>("peel_all0", m), ws.get<int32_t>("peel_all1", m)};
     u64 *rs = ws.get<u64>("peel_refill", 40);  // [0] count, [1] min, [2..34] histogram
 

@@ -102,6 +102,7 @@ struct PeelCounters {
 struct PeelOptions {
     const int32_t *fixed = nullptr;
     int32_t min_level = 0;
+    bool unit_updates = false;  // ablation: no batch bloom processing
 };
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s, const PeelOptions *opt = nullptr);
@@ -115,8 +116,9 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
 void mark_fixed(IndexArrays &ix, const int32_t *fixed, hipStream_t s);
 
 // Whole decompositions (api.hip): one graph, or many as disjoint unions.
+// `unit_updates`: the peel without batch bloom processing (ablation).
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
-                    Workspace &ws, hipStream_t stream);
+                    Workspace &ws, hipStream_t stream, bool unit_updates = false);
 void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
                           hipStream_t s);

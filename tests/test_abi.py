@@ -16,7 +16,8 @@ def declared_functions():
 
 def test_header_declares_entry_points():
     names = declared_functions()
-    for n in ("bt_support", "bt_index_build", "bt_decompose", "bt_decompose_pc",
+    for n in ("bt_support", "bt_index_build", "bt_decompose", "bt_decompose_variant",
+              "bt_decompose_pc",
               "bt_decompose_batch"):
         assert n in names
 

@@ -100,6 +100,29 @@ def test_scaled_chunglu_gpu(m):
     _parity(synth.scaled_chunglu(m, seed=3))
 
 
+def test_batch_edge_variant():
+    """BiT-BU+ (no batch bloom processing) gives the same numbers in the same
+    rounds; it issues one unit decrement per removed wedge and survivor,
+    which is what the batched peel counts as its unbatched updates."""
+    gs = [graphs.worked_example(True)[0], graphs.k2_1001(), synth.complete(7, 9),
+          synth.scaled_chunglu(20_000, seed=3)]
+    gs += [graphs.random_dense(30, 25, 0.6, s) for s in range(3)]
+    for g in gs:
+        dg = upload(g)
+        ophi = oracle_all(g)[2]
+        sb, pb, stb = binding.bt_decompose_variant(dg, binding.BT_PEEL_BATCH_BLOOM, stats=True)
+        se, pe, ste = binding.bt_decompose_variant(dg, binding.BT_PEEL_BATCH_EDGE, stats=True)
+        assert np.array_equal(pe.cpu().numpy(), ophi), g.name
+        assert np.array_equal(pb.cpu().numpy(), ophi), g.name
+        assert torch.equal(sb, se)
+        assert ste["rounds"] == stb["rounds"] and ste["levels"] == stb["levels"]
+        assert ste["support_updates"] == stb["support_updates_unbatched"], g.name
+        assert ste["support_updates"] >= stb["support_updates"]
+    with pytest.raises(binding.BtError) as ei:
+        binding.bt_decompose_variant(upload(gs[0]), 7)
+    assert ei.value.status == binding.BT_EINVAL
+
+
 def test_invalid_input_rejected():
     g = synth.uniform(10, 10, 30, 1)
     bad_col = g.col.copy()
