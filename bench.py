@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=512,
                     help="small graphs in the request pool (of the 4096)")
     ap.add_argument("--serve-big", type=int, default=4, help="2M-edge graphs in the request pool")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="autotune launch parameters (untimed) before measuring; 0 = defaults")
     ap.add_argument("--ablation", type=int, default=1,
                     help="also peel once without batch bloom processing (BiT-BU+); 0 = skip")
     ap.add_argument("--calib", action="store_true",
@@ -89,6 +91,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    tuning = {}
+    if args.tune:
+        t0 = time.perf_counter()
+        tuning["single"] = binding.bt_tune(dg)
+        tuning["single_seconds"] = round(time.perf_counter() - t0, 2)
+        print(f"[bench] tuned {tuning['single']}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         binding.bt_decompose(dg, stats=True, out_phi=phi, out_sup=sup)
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
@@ -167,12 +175,14 @@ def main():
     if args.ablation:
         out["ablation"] = ablation(dg, phi_h, st)
     if args.batch > 0:
-        out["batched"] = batch_compare(args.batch)
+        out["batched"] = batch_compare(args.batch, tuning if args.tune else None)
     if args.batch_all > 0:
         out["batched_all"] = batch_all(args.batch_all,
                                        out.get("batched", {}).get("plain_graphs_per_s"))
     if args.serve > 0:
         out["served"] = serve_compare(args.serve, args.serve_pool, args.serve_big)
+    if tuning:
+        out["tuning"] = tuning
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_frac)
@@ -197,8 +207,10 @@ def ablation(dg, phi_ref, st_bloom):
             if st_bloom["ms_peel_kernel"] else None}
 
 
-def batch_compare(n):
-    """Graphs/s of the batched form against the plain per-graph loop (same graphs)."""
+def batch_compare(n, tuning=None):
+    """Graphs/s of the batched form against the plain per-graph loop (same
+    graphs).  With `tuning`, batch launch parameters are tuned on these
+    graphs first (untimed) and recorded there."""
     import torch
     from paper_2001_06111_amd import binding, synth
     gs = [synth.batch_graph(i) for i in range(n)]
@@ -206,6 +218,11 @@ def batch_compare(n):
     m = sum(g.m for g in gs)
     binding.bt_decompose_batch(dgs[:8])
     binding.bt_decompose(dgs[0])
+    if tuning is not None:
+        t0 = time.perf_counter()
+        tuning["batch"] = binding.bt_tune(dgs)
+        tuning["batch_seconds"] = round(time.perf_counter() - t0, 2)
+        print(f"[bench] tuned batch {tuning['batch']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain = [binding.bt_decompose(d)[1] for d in dgs]

@@ -179,6 +179,60 @@ bt_status bt_decompose_variant(const bt_csr *g, int32_t variant, int64_t *sup_ou
                                int64_t *phi_out, bt_stats *stats, hipStream_t stream);
 
 /*
+ * Launch parameters.  They decide how the wedge sweeps cut start vertices
+ * into tasks and how many workgroups the sweeps and the peel run; no result
+ * depends on them.  The library keeps one entry per kind of call (a single
+ * graph, or a batch) and size class (bit_length(m) - 10, clamped to
+ * [0, 21]); a call uses its class's entry, else the nearest class of its
+ * kind that has one, else the defaults shown.  If the environment variable
+ * BT_TUNE_CACHE names a file written by bt_tune_save, it is loaded at the
+ * first lookup.  Not part of the paper: an implementation aid.
+ */
+typedef struct bt_tune_params {
+    int32_t hash_max_work;   /* start vertices with at most this many priority-obeyed
+                                wedges count them in one LDS hash task; [1, 2048], 2048 */
+    int32_t dense_chunk;     /* heavier start vertices count in dense ranges of this many
+                                end vertices, one workgroup each; [64, 6144], 6144 */
+    int32_t wedge_wg_per_cu; /* wedge-sweep workgroups per compute unit; [1, 16], 2 */
+    int32_t peel_blocks;     /* workgroups of the cooperative peel (0: one per compute
+                                unit; capped at what can be resident); [0, 65536], 0 */
+    int32_t active_min;      /* smallest active set the peel rebuilds; >= 1, 65536 */
+} bt_tune_params;
+
+enum { BT_TUNE_INDEX = 1, BT_TUNE_PEEL = 2 };
+
+/*
+ * Autotuner: times candidate values of each parameter in turn (coordinate
+ * search, the others held; a change must gain 2%) on these graphs, and
+ * stores the best in the entry of their kind and size class.  n_graphs ==
+ * 1 tunes single-graph calls (index parameters timed on the index build,
+ * peel parameters on the peel kernel); n_graphs > 1 tunes batches
+ * (bt_decompose_batch timed whole; class of the summed edge count).  `what`
+ * is a mask of BT_TUNE_INDEX and BT_TUNE_PEEL.  Runs several whole
+ * decompositions: seconds for a graph of millions of edges.
+ *   gs   host array of n_graphs device graphs.
+ *   out  host (nullable): the stored parameters.
+ * Errors as for bt_decompose / bt_decompose_batch; on an error the entry
+ * is left as it was.
+ */
+bt_status bt_tune(const bt_csr *gs, int32_t n_graphs, uint32_t what, bt_tune_params *out,
+                  hipStream_t stream);
+
+/* The parameters a call of this kind (batch: 0 or 1) and edge count uses. */
+bt_status bt_tune_get(int32_t batch, int64_t m, bt_tune_params *out);
+/* Sets the entry of this kind and size class (BT_EINVAL if out of range). */
+bt_status bt_tune_set(int32_t batch, int64_t m, const bt_tune_params *p);
+/* Forgets every entry (calls then use the defaults). */
+bt_status bt_tune_reset(void);
+/* Writes the entries to a text file: a header "bt-tune 1 <device arch>",
+ * then one line per entry "<single|batch> <class> <the five parameters>". */
+bt_status bt_tune_save(const char *path);
+/* Reads such a file and sets its entries (BT_EINVAL if it is malformed, has
+ * a value out of range, or was written for another device architecture;
+ * then no entry changes). */
+bt_status bt_tune_load(const char *path);
+
+/*
  * Bitruss numbers by progressive compression, BiT-PC (Section V-C,
  * Algorithms 6-7): for thresholds eps = k_max, k_max - alpha, ..., 0 with
  * alpha = ceil(k_max * tau) and k_max the largest k such that k edges have

@@ -49,10 +49,21 @@ class bt_index_info(ctypes.Structure):
         "m", "blooms", "bloom_wedges", "links", "butterflies", "wedges_po", "bytes")]
 
 
+class bt_tune_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "hash_max_work", "dense_chunk", "wedge_wg_per_cu", "peel_blocks", "active_min")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+BT_TUNE_INDEX, BT_TUNE_PEEL = 1, 2
+
 EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
             "bt_index_free", "bt_decompose", "bt_decompose_variant", "bt_decompose_pc",
             "bt_decompose_batch",
-            "bt_bitruss_components", "bt_release_workspace",
+            "bt_bitruss_components", "bt_release_workspace", "bt_tune", "bt_tune_get",
+            "bt_tune_set", "bt_tune_reset", "bt_tune_save", "bt_tune_load",
             "bt_last_error", "bt_version"]
 
 _lib = None
@@ -81,13 +92,21 @@ def load():
                                             ctypes.POINTER(i64), p]
         L.bt_decompose_batch.argtypes = [ctypes.POINTER(bt_csr), i32, ctypes.POINTER(p),
                                          ctypes.POINTER(p), ctypes.POINTER(bt_stats), p]
+        L.bt_tune.argtypes = [ctypes.POINTER(bt_csr), i32, ctypes.c_uint32,
+                              ctypes.POINTER(bt_tune_params), p]
+        L.bt_tune_get.argtypes = [i32, i64, ctypes.POINTER(bt_tune_params)]
+        L.bt_tune_set.argtypes = [i32, i64, ctypes.POINTER(bt_tune_params)]
+        L.bt_tune_reset.argtypes = []
+        L.bt_tune_save.argtypes = [ctypes.c_char_p]
+        L.bt_tune_load.argtypes = [ctypes.c_char_p]
         L.bt_release_workspace.restype = None
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
         for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
                      "bt_decompose", "bt_decompose_variant", "bt_decompose_pc",
                      "bt_decompose_batch",
-                     "bt_bitruss_components"):
+                     "bt_bitruss_components", "bt_tune", "bt_tune_get", "bt_tune_set",
+                     "bt_tune_reset", "bt_tune_save", "bt_tune_load"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -156,6 +175,40 @@ def bt_decompose(g: DeviceGraph, want_sup: bool = True, stats: bool = False, str
     _check(L.bt_decompose(ctypes.byref(c), _ptr(sup), _ptr(phi),
                           ctypes.byref(st) if stats else None, _stream(stream)))
     return sup, phi, (st.as_dict() if stats else None)
+
+
+def bt_tune(graphs, what: int = BT_TUNE_INDEX | BT_TUNE_PEEL, stream=None) -> dict:
+    """Autotune launch parameters on one DeviceGraph (single-graph calls) or a
+    list of them (batches); returns the stored parameters."""
+    L = load()
+    gl = graphs if isinstance(graphs, (list, tuple)) else [graphs]
+    arr = (bt_csr * len(gl))(*[g.csr() for g in gl])
+    out = bt_tune_params()
+    _check(L.bt_tune(arr, len(gl), ctypes.c_uint32(what), ctypes.byref(out), _stream(stream)))
+    return out.as_dict()
+
+
+def bt_tune_get(m: int, batch: bool = False) -> dict:
+    out = bt_tune_params()
+    _check(load().bt_tune_get(int(batch), int(m), ctypes.byref(out)))
+    return out.as_dict()
+
+
+def bt_tune_set(m: int, params: dict, batch: bool = False):
+    p = bt_tune_params(**{k: int(v) for k, v in params.items()})
+    _check(load().bt_tune_set(int(batch), int(m), ctypes.byref(p)))
+
+
+def bt_tune_reset():
+    _check(load().bt_tune_reset())
+
+
+def bt_tune_save(path: str):
+    _check(load().bt_tune_save(os.fsencode(path)))
+
+
+def bt_tune_load(path: str):
+    _check(load().bt_tune_load(os.fsencode(path)))
 
 
 BT_PEEL_BATCH_BLOOM, BT_PEEL_BATCH_EDGE = 0, 1

@@ -110,8 +110,10 @@ int64_t index_bytes(const IndexArrays &ix, int64_t m) {
 
 // prepare -> tasks -> counting + emission + links.  Reads back the sizes.
 void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
-               std::vector<void *> *own, Workspace &ws, hipStream_t s, Events *ev) {
+               std::vector<void *> *own, Workspace &ws, hipStream_t s, Events *ev,
+               bool batch = false) {
     prepare(g, r, ws, s);
+    if (batch) r.tp = tune_params(true, g.m);
     TaskLists t;
     make_tasks(r, t, ws, s);
     if (ev) ev->mark(1);
@@ -173,6 +175,17 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
     BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     BT_HIP(hipStreamSynchronize(stream));
     if (stats) fill_stats(stats, r, ix, pc, g.m, hs[0], ev);
+}
+
+float index_build_ms(const bt_csr &g, Workspace &ws, hipStream_t stream) {
+    Events ev(true, stream);
+    ev.mark(0);
+    RankCSR r;
+    IndexArrays ix;
+    build_all(g, r, ix, false, nullptr, ws, stream, &ev);
+    ev.mark(3);
+    BT_HIP(hipStreamSynchronize(stream));
+    return ev.ms(0, 3);
 }
 
 // BiT-PC (Section V-C, Algorithm 7).  Supports in G and k_max; then for
@@ -280,7 +293,7 @@ void decompose_union_impl(const bt_csr &u, const std::vector<int64_t> &off, int6
     ev.mark(0);
     RankCSR r;
     IndexArrays ix;
-    build_all(u, r, ix, false, nullptr, ws, s, &ev);
+    build_all(u, r, ix, false, nullptr, ws, s, &ev, off.size() > 2);
     ev.mark(3);
     PeelCounters pc;
     // Per-graph levels pay when there are several graphs, all small: its
@@ -612,6 +625,67 @@ bt_status bt_decompose_variant(const bt_csr *g, int32_t variant, int64_t *sup_ou
         std::lock_guard<std::mutex> lk(lib().mu);
         decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream,
                        variant == BT_PEEL_BATCH_EDGE);
+    });
+}
+
+namespace {
+bt::TuneParams from_c(const bt_tune_params &p) {
+    bt::TuneParams t;
+    t.hash_max_work = p.hash_max_work;
+    t.dense_chunk = p.dense_chunk;
+    t.wedge_wg_per_cu = p.wedge_wg_per_cu;
+    t.peel_blocks = p.peel_blocks;
+    t.active_min = p.active_min;
+    return t;
+}
+bt_tune_params to_c(const bt::TuneParams &t) {
+    return bt_tune_params{t.hash_max_work, t.dense_chunk, t.wedge_wg_per_cu, t.peel_blocks,
+                          t.active_min};
+}
+}  // namespace
+
+bt_status bt_tune(const bt_csr *gs, int32_t n_graphs, uint32_t what, bt_tune_params *out,
+                  hipStream_t stream) {
+    return guard([&] {
+        if (n_graphs < 1 || !gs) throw Error{BT_EINVAL, "bt_tune needs at least one graph"};
+        if (what & ~(uint32_t)(BT_TUNE_INDEX | BT_TUNE_PEEL))
+            throw Error{BT_EINVAL, "unknown bits in the tuning mask"};
+        for (int32_t i = 0; i < n_graphs; ++i) check_graph(&gs[i]);
+        std::lock_guard<std::mutex> lk(lib().mu);
+        const TuneParams t = autotune(gs, n_graphs, what, lib().ws, stream);
+        if (out) *out = to_c(t);
+    });
+}
+
+bt_status bt_tune_get(int32_t batch, int64_t m, bt_tune_params *out) {
+    return guard([&] {
+        if (!out || m < 0) throw Error{BT_EINVAL, "bt_tune_get: bad argument"};
+        *out = to_c(tune_params(batch != 0, m));
+    });
+}
+
+bt_status bt_tune_set(int32_t batch, int64_t m, const bt_tune_params *p) {
+    return guard([&] {
+        if (!p || m < 0) throw Error{BT_EINVAL, "bt_tune_set: bad argument"};
+        tune_store(batch != 0, m, from_c(*p));
+    });
+}
+
+bt_status bt_tune_reset(void) {
+    return guard([&] { tune_clear(); });
+}
+
+bt_status bt_tune_save(const char *path) {
+    return guard([&] {
+        if (!path) throw Error{BT_EINVAL, "path is NULL"};
+        tune_save(path);
+    });
+}
+
+bt_status bt_tune_load(const char *path) {
+    return guard([&] {
+        if (!path) throw Error{BT_EINVAL, "path is NULL"};
+        tune_load(path);
     });
 }
 

@@ -173,6 +173,7 @@ void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
     const int32_t nu = g.n_upper, nl = g.n_lower;
     const int64_t m = g.m;
     const int64_t n = (int64_t)nu + nl;
+    r.tp = tune_params(false, m);
     r.n_lower = nl;
     r.n = (int32_t)n;
     r.m = m;
@@ -242,29 +243,29 @@ void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
 
 namespace {
 
-constexpr int64_t kHashMaxWork = 2048;  // hash tasks: at most this many wedges
-constexpr int32_t kDenseChunk = 6144;   // dense tasks: counter range per workgroup
-
 __device__ __forceinline__ int64_t vertex_work(const int64_t *off, const int32_t *low,
                                                const int64_t *wpre, int32_t x) {
     return wpre[off[x] + low[x]] - wpre[off[x]];
 }
 
-__device__ __forceinline__ int32_t dense_chunks(int32_t x, int32_t n_lower) {
+// Start vertices with more than hash_max wedges count their end vertices
+// in dense ranges of `chunk` counters, one task per range.
+__device__ __forceinline__ int32_t dense_chunks(int32_t x, int32_t n_lower, int32_t chunk) {
     const int32_t base = x >= n_lower ? n_lower : 0;
     const int32_t span = x - base;
-    return (span + kDenseChunk - 1) / kDenseChunk;
+    return (span + chunk - 1) / chunk;
 }
 
 __global__ void k_task_count(const int64_t *off, const int32_t *low, const int64_t *wpre,
-                             int32_t n, int32_t n_lower, int64_t *counts) {
+                             int32_t n, int32_t n_lower, int32_t hash_max, int32_t chunk,
+                             int64_t *counts) {
     int64_t nh = 0, nd = 0;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
         const int64_t w = vertex_work(off, low, wpre, (int32_t)x);
         if (w == 0) continue;
-        if (w <= kHashMaxWork) ++nh;
-        else nd += dense_chunks((int32_t)x, n_lower);
+        if (w <= hash_max) ++nh;
+        else nd += dense_chunks((int32_t)x, n_lower, chunk);
     }
     nh = wave_sum(nh);
     nd = wave_sum(nd);
@@ -275,25 +276,25 @@ __global__ void k_task_count(const int64_t *off, const int32_t *low, const int64
 }
 
 __global__ void k_task_fill(const int64_t *off, const int32_t *low, const int64_t *wpre,
-                            int32_t n, int32_t n_lower, WedgeTask *hash, WedgeTask *dense,
-                            int32_t *cursors) {
+                            int32_t n, int32_t n_lower, int32_t hash_max, int32_t chunk,
+                            WedgeTask *hash, WedgeTask *dense, int32_t *cursors) {
     for (int64_t xi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; xi < n;
          xi += (int64_t)gridDim.x * blockDim.x) {
         const int32_t x = (int32_t)xi;
         const int64_t w = vertex_work(off, low, wpre, x);
         if (w == 0) continue;
-        if (w <= kHashMaxWork) {
+        if (w <= hash_max) {
             int32_t cap = 128;
             while (cap < 2 * w) cap <<= 1;
             const int32_t p = atomicAdd(&cursors[0], 1);
             hash[p] = WedgeTask{x, 0, 0, cap};
         } else {
             const int32_t base = x >= n_lower ? n_lower : 0;
-            const int32_t nc = dense_chunks(x, n_lower);
+            const int32_t nc = dense_chunks(x, n_lower, chunk);
             const int32_t p = atomicAdd(&cursors[1], nc);
             for (int32_t c = 0; c < nc; ++c) {
-                const int32_t lo = base + c * kDenseChunk;
-                const int32_t hi = min(lo + kDenseChunk, x);
+                const int32_t lo = base + c * chunk;
+                const int32_t hi = min(lo + chunk, x);
                 dense[p + c] = WedgeTask{x, lo, hi, hi - lo};
             }
         }
@@ -304,11 +305,12 @@ __global__ void k_task_fill(const int64_t *off, const int32_t *low, const int64_
 
 void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
     RankCSR &r = const_cast<RankCSR &>(rc);
+    if (!tune_valid(r.tp)) throw Error{BT_EINVAL, "invalid launch parameters"};
     int64_t *counts = ws.get<int64_t>("task_counts", 4);
     BT_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(int64_t), s));
     if (r.n > 0) {
-        k_task_count<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(r.off, r.low, r.wpre, r.n,
-                                                              r.n_lower, counts);
+        k_task_count<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(
+            r.off, r.low, r.wpre, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk, counts);
         BT_CHECK_LAUNCH();
     }
     int64_t *hs = ws.host(4);
@@ -325,8 +327,9 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
     int32_t *cur = ws.get<int32_t>("task_cursor", 2);
     BT_HIP(hipMemsetAsync(cur, 0, 2 * sizeof(int32_t), s));
     if (r.n > 0 && (t.n_hash + t.n_dense) > 0) {
-        k_task_fill<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(r.off, r.low, r.wpre, r.n,
-                                                             r.n_lower, t.hash, t.dense, cur);
+        k_task_fill<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(
+            r.off, r.low, r.wpre, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk, t.hash,
+            t.dense, cur);
         BT_CHECK_LAUNCH();
     }
 }

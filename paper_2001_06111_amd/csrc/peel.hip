@@ -727,6 +727,7 @@ struct RefillArgs {
     RefillState *rs;
     int32_t *list[2];
     int32_t min_level;  // progressive mode: the first level is at least this
+    int32_t active_min;  // the set holds at least this many edges (or all)
 };
 
 // Reserves `keep` slots of *ctr for each thread, one atomic per workgroup.
@@ -819,10 +820,10 @@ __device__ int64_t grid_refill(const PeelArgs &P, const RefillArgs &RA, GridBar 
     __syncthreads();
     if (threadIdx.x == 0) {
         s_ok2 = grid_arrive_wait(B, gen_local);
-        // Threshold: the set holds at least max(65536, n / 32) edges, and every
-        // edge at or below the first level.
+        // Threshold: the set holds at least max(active_min, n / 32) edges, and
+        // every edge at or below the first level.
         const int32_t lvl = max(m0, RA.min_level);
-        const int64_t target = max((int64_t)65536, n / 32);
+        const int64_t target = max((int64_t)RA.active_min, n / 32);
         int64_t T = INT_MAX, acc = 0;
         for (int b = 0; b < 33; ++b) {
             acc += (int64_t)ld(&RS->hist[b]);
@@ -1554,7 +1555,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_persistent, kPBlock, 0));
         const char *pb = std::getenv("BT_PEEL_PBLOCKS");
-        pblocks = pb ? std::atoi(pb) : cus;  // one block per CU
+        pblocks = pb ? std::atoi(pb) : (r.tp.peel_blocks > 0 ? r.tp.peel_blocks : cus);
         pblocks = std::max(1, std::min(pblocks, occ * cus));
     }
 
@@ -1579,7 +1580,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         rs0.n_all = m;
         RefillState *drs = ws.get<RefillState>("peel_refill_state", 1);
         BT_HIP(hipMemcpyAsync(drs, &rs0, sizeof rs0, hipMemcpyHostToDevice, s));
-        RefillArgs RA{drs, {glist[0], glist[1]}, min_level};
+        RefillArgs RA{drs, {glist[0], glist[1]}, min_level, r.tp.active_min};
         int64_t max_rounds = 4 * m + 64;
         int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
         void *args[] = {&P, &bar, &max_rounds, &prof, &RA};
@@ -1631,7 +1632,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             BT_CHECK_LAUNCH();
             BT_HIP(hipMemcpyAsync(hr + 2, rs + 2, 33 * sizeof(u64), hipMemcpyDeviceToHost, s));
             BT_HIP(hipStreamSynchronize(s));
-            const int64_t target = std::max<int64_t>(65536, n_all / 32);
+            const int64_t target = std::max<int64_t>(r.tp.active_min, n_all / 32);
             int64_t thresh = INT_MAX, acc = 0;
             for (int b = 0; b < 33; ++b) {
                 acc += (int64_t)hr[2 + b];
@@ -1806,7 +1807,8 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
     BT_HIP(hipGetDevice(&dev));
     BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_multi, kPBlock, 0));
-    const int pblocks = std::max(1, std::min(cus, occ * cus));
+    const int pblocks =
+        std::max(1, std::min(r.tp.peel_blocks > 0 ? r.tp.peel_blocks : cus, occ * cus));
     int64_t max_rounds = 8 * m + 64;
     int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
     std::lock_guard<std::mutex> coop_lock(coop_mutex());

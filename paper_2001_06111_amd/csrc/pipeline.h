@@ -18,7 +18,28 @@ namespace bt {
 // position of x in row y, which is the number of y's neighbours of lower
 // priority than x: the wedges (x, y, z) with p(y), p(z) < p(x) are
 // exactly z = adj[off[y] + t] for t < rev.
+// Launch parameters of the sweeps and the peel.  None of them changes a
+// result; the autotuner (tune.hip) picks them per kind of call (one graph,
+// or a batch) and per size class, and prepare() copies the entry for the
+// graph into its RankCSR.
+struct TuneParams {
+    int32_t hash_max_work = 2048;  // start vertices with at most this many wedges: one hash task
+    int32_t dense_chunk = 6144;    // counter range of a dense task (hub start vertices)
+    int32_t wedge_wg_per_cu = 2;   // wedge-sweep workgroups per CU
+    int32_t peel_blocks = 0;       // persistent peel workgroups (0: one per CU)
+    int32_t active_min = 65536;    // smallest active set the peel rebuilds
+};
+constexpr int32_t kHashMaxWorkLimit = 2048;  // hash tables hold at most 4096 slots
+constexpr int32_t kDenseChunkLimit = 6144;   // dense counters per workgroup in LDS
+bool tune_valid(const TuneParams &p);
+TuneParams tune_params(bool batch, int64_t m);  // the entry for a call of this kind and size
+void tune_store(bool batch, int64_t m, const TuneParams &p);  // throws BT_EINVAL if invalid
+void tune_clear();
+void tune_save(const char *path);
+void tune_load(const char *path);
+
 struct RankCSR {
+    TuneParams tp;
     int32_t n_lower = 0, n = 0;
     int64_t m = 0;
     int64_t *off = nullptr;   // [n + 1]
@@ -119,6 +140,11 @@ void mark_fixed(IndexArrays &ix, const int32_t *fixed, hipStream_t s);
 // `unit_updates`: the peel without batch bloom processing (ablation).
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
                     Workspace &ws, hipStream_t stream, bool unit_updates = false);
+// Measures candidate launch parameters on these graphs (one graph, or a
+// batch) and stores the best for their kind and size class (tune.hip).
+TuneParams autotune(const bt_csr *gs, int32_t n, uint32_t what, Workspace &ws, hipStream_t s);
+// Device time of the index build alone (priority order, sweeps, links).
+float index_build_ms(const bt_csr &g, Workspace &ws, hipStream_t stream);
 void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
                           hipStream_t s);

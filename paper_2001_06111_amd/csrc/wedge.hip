@@ -59,6 +59,8 @@ constexpr size_t kTableBytes = (size_t)kHashCapMax * 12 > (size_t)kDenseCapMax *
                                    ? (size_t)kHashCapMax * 12
                                    : (size_t)kDenseCapMax * 8;
 constexpr size_t kSmemBytes = sizeof(Smem) + kTableBytes;
+static_assert(kHashCapMax >= 2 * kHashMaxWorkLimit, "a hash task's table must fit");
+static_assert(kDenseCapMax >= kDenseChunkLimit, "a dense task's range must fit");
 
 __device__ __forceinline__ uint32_t hash32(int32_t z) {
     return (uint32_t)z * 2654435761u;
@@ -308,13 +310,14 @@ __global__ void k_bloom_sentinel(const uint64_t *cursor, uint32_t *bwoff) {
 }
 
 template <bool DENSE, bool INDEX>
-void launch_wedge(const WedgeArgs &A, const WedgeTask *tasks, int64_t n, hipStream_t s) {
+void launch_wedge(const WedgeArgs &A, const WedgeTask *tasks, int64_t n, int wg_per_cu,
+                  hipStream_t s) {
     if (n <= 0) return;
     BT_HIP(hipMemsetAsync(A.queue, 0, sizeof(int64_t), s));
     int dev = 0, cus = 0;
     BT_HIP(hipGetDevice(&dev));
     BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t grid = std::min<int64_t>(n, (int64_t)cus * 2);
+    const int64_t grid = std::min<int64_t>(n, (int64_t)cus * wg_per_cu);
     k_wedge<DENSE, INDEX><<<(unsigned)grid, kWG, kSmemBytes, s>>>(A, tasks, n);
     BT_CHECK_LAUNCH();
 }
@@ -345,8 +348,8 @@ void count_support(const RankCSR &r, const TaskLists &t, uint64_t *supl, int64_t
     static_assert(kSmemBytes <= 65536, "LDS budget");
     int64_t *queue = reinterpret_cast<int64_t *>(bf) + 1;  // caller gives 2 scalars
     WedgeArgs A = make_args(r, supl, bf, queue);
-    launch_wedge<true, false>(A, t.dense, t.n_dense, s);
-    launch_wedge<false, false>(A, t.hash, t.n_hash, s);
+    launch_wedge<true, false>(A, t.dense, t.n_dense, r.tp.wedge_wg_per_cu, s);
+    launch_wedge<false, false>(A, t.hash, t.n_hash, r.tp.wedge_wg_per_cu, s);
 }
 
 void build_index(const RankCSR &r, const TaskLists &t, IndexArrays &ix, Workspace &ws,
@@ -359,8 +362,8 @@ void build_index(const RankCSR &r, const TaskLists &t, IndexArrays &ix, Workspac
     A.wea = ix.wea;
     A.web = ix.web;
     A.wbl = ix.wbl;
-    launch_wedge<true, true>(A, t.dense, t.n_dense, s);
-    launch_wedge<false, true>(A, t.hash, t.n_hash, s);
+    launch_wedge<true, true>(A, t.dense, t.n_dense, r.tp.wedge_wg_per_cu, s);
+    launch_wedge<false, true>(A, t.hash, t.n_hash, r.tp.wedge_wg_per_cu, s);
     k_bloom_sentinel<<<1, 1, 0, s>>>(ix.cursor, ix.bwoff);
     BT_CHECK_LAUNCH();
 
