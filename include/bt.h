@@ -194,9 +194,10 @@ typedef struct bt_tune_params {
     int32_t dense_chunk;     /* heavier start vertices count in dense ranges of this many
                                 end vertices, one workgroup each; [64, 6144], 6144 */
     int32_t wedge_wg_per_cu; /* wedge-sweep workgroups per compute unit; [1, 16], 2 */
-    int32_t peel_blocks;     /* workgroups of the cooperative peel (0: one per compute
-                                unit; capped at what can be resident); [0, 65536], 0 */
-    int32_t active_min;      /* smallest active set the peel rebuilds; >= 1, 65536 */
+    int32_t peel_blocks;     /* workgroups of the cooperative peel (0: three per four
+                                compute units; capped at what can be resident);
+                                [0, 65536], 0 */
+    int32_t active_min;      /* smallest active set the peel rebuilds; >= 1, 16384 */
 } bt_tune_params;
 
 enum { BT_TUNE_INDEX = 1, BT_TUNE_PEEL = 2 };

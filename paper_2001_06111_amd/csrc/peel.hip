@@ -1555,8 +1555,8 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_persistent, kPBlock, 0));
         const char *pb = std::getenv("BT_PEEL_PBLOCKS");
-        pblocks = pb ? std::atoi(pb) : (r.tp.peel_blocks > 0 ? r.tp.peel_blocks : cus);
-        pblocks = std::max(1, std::min(pblocks, occ * cus));
+        pblocks = pb ? std::max(1, std::min(std::atoi(pb), occ * cus))
+                     : peel_grid(r.tp, cus, occ * cus);
     }
 
     std::unique_lock<std::mutex> coop_lock(coop_mutex(), std::defer_lock);
@@ -1807,8 +1807,7 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
     BT_HIP(hipGetDevice(&dev));
     BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_multi, kPBlock, 0));
-    const int pblocks =
-        std::max(1, std::min(r.tp.peel_blocks > 0 ? r.tp.peel_blocks : cus, occ * cus));
+    const int pblocks = peel_grid(r.tp, cus, occ * cus);
     int64_t max_rounds = 8 * m + 64;
     int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
     std::lock_guard<std::mutex> coop_lock(coop_mutex());

@@ -26,12 +26,16 @@ struct TuneParams {
     int32_t hash_max_work = 2048;  // start vertices with at most this many wedges: one hash task
     int32_t dense_chunk = 6144;    // counter range of a dense task (hub start vertices)
     int32_t wedge_wg_per_cu = 2;   // wedge-sweep workgroups per CU
-    int32_t peel_blocks = 0;       // persistent peel workgroups (0: one per CU)
-    int32_t active_min = 65536;    // smallest active set the peel rebuilds
+    int32_t peel_blocks = 0;       // persistent peel workgroups (0: three per four CUs)
+    int32_t active_min = 16384;    // smallest active set the peel rebuilds
 };
 constexpr int32_t kHashMaxWorkLimit = 2048;  // hash tables hold at most 4096 slots
 constexpr int32_t kDenseChunkLimit = 6144;   // dense counters per workgroup in LDS
 bool tune_valid(const TuneParams &p);
+// Workgroups of a cooperative peel: the parameter, or three per four CUs
+// (fewer arrivals per grid barrier; a round rarely fills the chip), capped
+// at what can be resident.
+int peel_grid(const TuneParams &p, int cus, int resident);
 TuneParams tune_params(bool batch, int64_t m);  // the entry for a call of this kind and size
 void tune_store(bool batch, int64_t m, const TuneParams &p);  // throws BT_EINVAL if invalid
 void tune_clear();

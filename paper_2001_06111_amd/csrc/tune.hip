@@ -117,6 +117,11 @@ bool tune_valid(const TuneParams &p) {
            p.active_min >= 1;
 }
 
+int peel_grid(const TuneParams &p, int cus, int resident) {
+    const int want = p.peel_blocks > 0 ? p.peel_blocks : std::max(1, 3 * cus / 4);
+    return std::max(1, std::min(want, resident));
+}
+
 TuneParams tune_params(bool batch, int64_t m) {
     Table &t = table();
     std::lock_guard<std::mutex> lk(t.mu);
@@ -257,8 +262,8 @@ TuneParams autotune(const bt_csr *gs, int32_t n, uint32_t what, Workspace &ws, h
         knobs.push_back({&TuneParams::wedge_wg_per_cu, {1, 2}, false});
     }
     if (what & BT_TUNE_PEEL) {
-        knobs.push_back({&TuneParams::peel_blocks, {cus / 2, 3 * cus / 4, 0}, true});
-        knobs.push_back({&TuneParams::active_min, {16384, 65536, 262144}, true});
+        knobs.push_back({&TuneParams::peel_blocks, {cus / 2, 0, cus}, true});
+        knobs.push_back({&TuneParams::active_min, {4096, 16384, 65536}, true});
     }
     static const char *const names[] = {"hash_max_work", "dense_chunk", "wedge_wg_per_cu",
                                         "peel_blocks", "active_min"};

@@ -10,7 +10,7 @@ from tests.gpu_util import oracle_all, upload
 pytestmark = pytest.mark.gpu
 
 DEFAULTS = {"hash_max_work": 2048, "dense_chunk": 6144, "wedge_wg_per_cu": 2, "peel_blocks": 0,
-            "active_min": 65536}
+            "active_min": 16384}
 # Extremes: every start vertex dense in ranges of 64, one sweep workgroup per
 # CU, an 8-workgroup peel rebuilding an active set of one edge.
 EXTREMES = [

@@ -6,7 +6,7 @@ import pytest
 from paper_2001_06111_amd import binding
 
 DEFAULTS = {"hash_max_work": 2048, "dense_chunk": 6144, "wedge_wg_per_cu": 2, "peel_blocks": 0,
-            "active_min": 65536}
+            "active_min": 16384}
 
 
 @pytest.fixture(autouse=True)
