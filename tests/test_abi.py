@@ -31,3 +31,48 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_without_gpu():
     assert binding.bt_version().startswith("bt-mi355x")
+
+
+def _csr(nu=3, nl=4, m=5, rp=0x1000, col=0x2000):
+    return binding.bt_csr(nu, nl, m, rp, col)
+
+
+def test_argument_errors_without_gpu():
+    """Malformed descriptors and arguments are rejected before any device
+    work, with the documented status and a message."""
+    L = binding.load()
+    P = ctypes.c_void_p
+    fake = P(0x3000)
+    cases = [
+        (lambda: L.bt_decompose(None, None, fake, None, None), binding.BT_EINVAL),
+        (lambda: L.bt_decompose(ctypes.byref(_csr(m=-1)), None, fake, None, None),
+         binding.BT_EINVAL),
+        (lambda: L.bt_decompose(ctypes.byref(_csr(nu=-2)), None, fake, None, None),
+         binding.BT_EINVAL),
+        (lambda: L.bt_decompose(ctypes.byref(_csr(nu=2**31 - 1, nl=1)), None, fake, None, None),
+         binding.BT_EOVERFLOW),
+        (lambda: L.bt_decompose(ctypes.byref(_csr(m=2**31)), None, fake, None, None),
+         binding.BT_EOVERFLOW),
+        (lambda: L.bt_decompose(ctypes.byref(_csr(rp=None)), None, fake, None, None),
+         binding.BT_EINVAL),
+        (lambda: L.bt_decompose(ctypes.byref(_csr(col=None)), None, fake, None, None),
+         binding.BT_EINVAL),
+        (lambda: L.bt_decompose(ctypes.byref(_csr()), None, None, None, None), binding.BT_EINVAL),
+        (lambda: L.bt_decompose_variant(ctypes.byref(_csr()), 5, None, fake, None, None),
+         binding.BT_EINVAL),
+        (lambda: L.bt_decompose_pc(ctypes.byref(_csr()), ctypes.c_double(0.0), None, fake,
+                                   None, None), binding.BT_EINVAL),
+        (lambda: L.bt_decompose_pc(ctypes.byref(_csr()), ctypes.c_double(1.5), None, fake,
+                                   None, None), binding.BT_EINVAL),
+        (lambda: L.bt_decompose_batch(None, -1, None, None, None, None), binding.BT_EINVAL),
+        (lambda: L.bt_bitruss_components(ctypes.byref(_csr()), None, 1, fake, None, None),
+         binding.BT_EINVAL),
+        (lambda: L.bt_tune(ctypes.byref(_csr()), 0, 3, None, None), binding.BT_EINVAL),
+        (lambda: L.bt_tune(ctypes.byref(_csr()), 1, 8, None, None), binding.BT_EINVAL),
+        (lambda: L.bt_tune_get(0, -1, None), binding.BT_EINVAL),
+    ]
+    for i, (call, want) in enumerate(cases):
+        rc = call()
+        msg = L.bt_last_error().decode()
+        assert rc == want, (i, rc, msg)
+        assert msg, i
