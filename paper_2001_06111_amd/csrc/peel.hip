@@ -653,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
 
 // --- persistent cooperative kernel: rounds separated by grid barriers ---
 
-constexpr int kPBlock = 1024;  // 16 waves per CU (108 VGPRs fit four waves per SIMD)
+constexpr int kPBlock = 1024;  // 16 waves per CU (up to 128 VGPRs: four waves per SIMD)
 
 struct GridBar {
     Counter group[8];  // arrivals per group (monotonic)
@@ -709,7 +709,7 @@ __device__ bool grid_arrive_wait(GridBar *B, u64 &k) {
 // dry: the remaining edges (phi < 0) are compacted from one list into the
 // other while their minimum support mn is found; a log2 histogram of
 // support - mn picks the threshold T that puts a few percent of them (at
-// least 65,536) in the active set; the edges below T are gathered into
+// least active_min) in the active set; the edges below T are gathered into
 // active buffer 0; and the round state is set as if the previous round had
 // been a gather that saw minimum support mn.  Counters are pooled per
 // workgroup.  Every workgroup derives T from the same histogram.
