@@ -111,8 +111,8 @@ int64_t index_bytes(const IndexArrays &ix, int64_t m) {
 // prepare -> tasks -> counting + emission + links.  Reads back the sizes.
 void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
                std::vector<void *> *own, Workspace &ws, hipStream_t s, Events *ev,
-               bool batch = false) {
-    prepare(g, r, ws, s);
+               bool batch = false, const Components *comps = nullptr) {
+    prepare(g, r, ws, s, comps);
     if (batch) r.tp = tune_params(true, g.m);
     TaskLists t;
     make_tasks(r, t, ws, s);
@@ -287,13 +287,14 @@ constexpr int64_t kMultiMaxEdges = int64_t(1) << 19;
 
 // A disjoint union of graphs (edge ranges [off[g], off[g+1])): one index
 // build for the union, then one peel in which every graph has its own level.
-void decompose_union_impl(const bt_csr &u, const std::vector<int64_t> &off, int64_t *sup_out,
-                          int64_t *phi_out, bt_stats *stats, Workspace &ws, hipStream_t s) {
+void decompose_union_impl(const bt_csr &u, const std::vector<int64_t> &off,
+                          const Components &comps, int64_t *sup_out, int64_t *phi_out,
+                          bt_stats *stats, Workspace &ws, hipStream_t s) {
     Events ev(stats != nullptr, s);
     ev.mark(0);
     RankCSR r;
     IndexArrays ix;
-    build_all(u, r, ix, false, nullptr, ws, s, &ev, off.size() > 2);
+    build_all(u, r, ix, false, nullptr, ws, s, &ev, off.size() > 2, &comps);
     ev.mark(3);
     PeelCounters pc;
     // Per-graph levels pay when there are several graphs, all small: its
@@ -446,9 +447,24 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
     std::vector<int64_t> off(b - a + 1);
     for (int32_t i = a; i < b; ++i) off[i - a] = tab[i - a].m_off;
     off[b - a] = m;
+    // Vertex ranges of the graphs, lower then upper offsets.
+    std::vector<int64_t> voff(2 * (size_t)(b - a + 1));
+    for (int32_t i = a; i < b; ++i) {
+        voff[i - a] = tab[i - a].nl_off;
+        voff[(b - a + 1) + (i - a)] = tab[i - a].nu_off;
+    }
+    voff[b - a] = nl;
+    voff[2 * (b - a) + 1] = nu;
+    int64_t *dvoff = ws.get<int64_t>("batch_voff", (int64_t)voff.size());
+    BT_HIP(hipMemcpyAsync(dvoff, voff.data(), sizeof(int64_t) * voff.size(),
+                          hipMemcpyHostToDevice, s));
+    Components comps;
+    comps.n = b - a;
+    comps.l_off = dvoff;
+    comps.u_off = dvoff + (b - a + 1);
     bt_stats st;
     try {
-        decompose_union_impl(u, off, sup_u, phi_u, stats ? &st : nullptr, ws, s);
+        decompose_union_impl(u, off, comps, sup_u, phi_u, stats ? &st : nullptr, ws, s);
     } catch (const Error &e) {
         if (e.status != BT_EOVERFLOW || !splittable) throw;
         const int32_t mid = a + (b - a) / 2;

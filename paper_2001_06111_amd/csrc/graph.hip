@@ -65,6 +65,41 @@ __global__ void k_rank_keys(const int32_t *deg, int32_t n_lower, int32_t n, uint
     }
 }
 
+// Graph of vertex v in a union (offsets of its layer, n + 1 entries).
+__device__ __forceinline__ int32_t comp_of(const int64_t *off, int32_t n, int64_t local) {
+    int32_t lo = 0, hi = n - 1;  // largest c with off[c] <= local
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) / 2;
+        if (off[mid] <= local) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Union: layer above graph above degree; the stable sort keeps id order.
+__global__ void k_rank_keys_comp(const int32_t *deg, int32_t n_lower, int32_t n, Components cp,
+                                 int cbits, uint64_t *keys, uint32_t *vals) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const bool up = v >= n_lower;
+        const int32_t c = up ? comp_of(cp.u_off, cp.n, v - n_lower) : comp_of(cp.l_off, cp.n, v);
+        keys[v] = ((uint64_t)up << (31 + cbits)) | ((uint64_t)c << 31) | (uint64_t)deg[v];
+        vals[v] = (uint32_t)v;
+    }
+}
+
+// zbase[p]: the first rank of p's graph in p's layer.
+__global__ void k_zbase(const int32_t *new2old, int32_t n_lower, int32_t n, Components cp,
+                        int32_t *zbase) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = new2old[p];
+        const bool up = v >= n_lower;
+        const int32_t c = up ? comp_of(cp.u_off, cp.n, v - n_lower) : comp_of(cp.l_off, cp.n, v);
+        zbase[p] = up ? n_lower + (int32_t)cp.u_off[c] : (int32_t)cp.l_off[c];
+    }
+}
+
 __global__ void k_rank_apply(const uint32_t *order, const int32_t *deg, int32_t n,
                              int32_t *old2new, int32_t *new2old, int32_t *deg_new) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
@@ -169,7 +204,8 @@ void validate_graph(const bt_csr &g, Workspace &ws, hipStream_t s) {
         throw Error{BT_EINVAL, "lower ids not strictly increasing within a row (duplicate edge?)"};
 }
 
-void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
+void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s,
+             const Components *comps) {
     const int32_t nu = g.n_upper, nl = g.n_lower;
     const int64_t m = g.m;
     const int64_t n = (int64_t)nu + nl;
@@ -196,13 +232,30 @@ void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s) {
     int32_t *old2new = ws.get<int32_t>("prep_old2new", n);
     int32_t *new2old = ws.get<int32_t>("prep_new2old", n);
     int32_t *deg_new = ws.get<int32_t>("prep_degnew", n);
+    const bool uni = comps && comps->n > 1;
+    r.zbase = nullptr;
     if (n > 0) {
-        k_rank_keys<<<grid_for(n, 256, 8192), 256, 0, s>>>(deg, nl, (int32_t)n, vkeys, vorder);
-        BT_CHECK_LAUNCH();
-        radix_sort_u64_u32(vkeys, vorder, n, 32, ws, s);
+        if (uni) {
+            const int cbits = bits_for((uint64_t)(comps->n - 1));
+            k_rank_keys_comp<<<grid_for(n, 256, 8192), 256, 0, s>>>(deg, nl, (int32_t)n, *comps,
+                                                                   cbits, vkeys, vorder);
+            BT_CHECK_LAUNCH();
+            radix_sort_u64_u32(vkeys, vorder, n, 32 + cbits, ws, s);
+        } else {
+            k_rank_keys<<<grid_for(n, 256, 8192), 256, 0, s>>>(deg, nl, (int32_t)n, vkeys,
+                                                              vorder);
+            BT_CHECK_LAUNCH();
+            radix_sort_u64_u32(vkeys, vorder, n, 32, ws, s);
+        }
         k_rank_apply<<<grid_for(n, 256, 8192), 256, 0, s>>>(vorder, deg, (int32_t)n, old2new,
                                                             new2old, deg_new);
         BT_CHECK_LAUNCH();
+        if (uni) {
+            r.zbase = ws.get<int32_t>("rank_zbase", n);
+            k_zbase<<<grid_for(n, 256, 8192), 256, 0, s>>>(new2old, nl, (int32_t)n, *comps,
+                                                           r.zbase);
+            BT_CHECK_LAUNCH();
+        }
     }
     r.off = ws.get<int64_t>("rank_off", n + 1);
     scan_exclusive_i32_to_i64(deg_new, r.off, n, ws, s);
@@ -249,23 +302,25 @@ __device__ __forceinline__ int64_t vertex_work(const int64_t *off, const int32_t
 }
 
 // Start vertices with more than hash_max wedges count their end vertices
-// in dense ranges of `chunk` counters, one task per range.
-__device__ __forceinline__ int32_t dense_chunks(int32_t x, int32_t n_lower, int32_t chunk) {
-    const int32_t base = x >= n_lower ? n_lower : 0;
-    const int32_t span = x - base;
-    return (span + chunk - 1) / chunk;
+// in dense ranges of `chunk` counters, one task per range, over the ranks
+// below x in x's layer (in a union, x's graph's part of it).
+__device__ __forceinline__ int32_t z_base(const int32_t *zbase, int32_t x, int32_t n_lower) {
+    return zbase ? zbase[x] : (x >= n_lower ? n_lower : 0);
+}
+__device__ __forceinline__ int32_t dense_chunks(int32_t x, int32_t base, int32_t chunk) {
+    return (x - base + chunk - 1) / chunk;
 }
 
 __global__ void k_task_count(const int64_t *off, const int32_t *low, const int64_t *wpre,
-                             int32_t n, int32_t n_lower, int32_t hash_max, int32_t chunk,
-                             int64_t *counts) {
+                             const int32_t *zbase, int32_t n, int32_t n_lower, int32_t hash_max,
+                             int32_t chunk, int64_t *counts) {
     int64_t nh = 0, nd = 0;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
          x += (int64_t)gridDim.x * blockDim.x) {
         const int64_t w = vertex_work(off, low, wpre, (int32_t)x);
         if (w == 0) continue;
         if (w <= hash_max) ++nh;
-        else nd += dense_chunks((int32_t)x, n_lower, chunk);
+        else nd += dense_chunks((int32_t)x, z_base(zbase, (int32_t)x, n_lower), chunk);
     }
     nh = wave_sum(nh);
     nd = wave_sum(nd);
@@ -276,8 +331,9 @@ __global__ void k_task_count(const int64_t *off, const int32_t *low, const int64
 }
 
 __global__ void k_task_fill(const int64_t *off, const int32_t *low, const int64_t *wpre,
-                            int32_t n, int32_t n_lower, int32_t hash_max, int32_t chunk,
-                            WedgeTask *hash, WedgeTask *dense, int32_t *cursors) {
+                            const int32_t *zbase, int32_t n, int32_t n_lower, int32_t hash_max,
+                            int32_t chunk, WedgeTask *hash, WedgeTask *dense,
+                            int32_t *cursors) {
     for (int64_t xi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; xi < n;
          xi += (int64_t)gridDim.x * blockDim.x) {
         const int32_t x = (int32_t)xi;
@@ -289,8 +345,8 @@ __global__ void k_task_fill(const int64_t *off, const int32_t *low, const int64_
             const int32_t p = atomicAdd(&cursors[0], 1);
             hash[p] = WedgeTask{x, 0, 0, cap};
         } else {
-            const int32_t base = x >= n_lower ? n_lower : 0;
-            const int32_t nc = dense_chunks(x, n_lower, chunk);
+            const int32_t base = z_base(zbase, x, n_lower);
+            const int32_t nc = dense_chunks(x, base, chunk);
             const int32_t p = atomicAdd(&cursors[1], nc);
             for (int32_t c = 0; c < nc; ++c) {
                 const int32_t lo = base + c * chunk;
@@ -310,7 +366,8 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
     BT_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(int64_t), s));
     if (r.n > 0) {
         k_task_count<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(
-            r.off, r.low, r.wpre, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk, counts);
+            r.off, r.low, r.wpre, r.zbase, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk,
+            counts);
         BT_CHECK_LAUNCH();
     }
     int64_t *hs = ws.host(4);
@@ -328,8 +385,8 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
     BT_HIP(hipMemsetAsync(cur, 0, 2 * sizeof(int32_t), s));
     if (r.n > 0 && (t.n_hash + t.n_dense) > 0) {
         k_task_fill<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(
-            r.off, r.low, r.wpre, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk, t.hash,
-            t.dense, cur);
+            r.off, r.low, r.wpre, r.zbase, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk,
+            t.hash, t.dense, cur);
         BT_CHECK_LAUNCH();
     }
 }

@@ -42,6 +42,15 @@ void tune_clear();
 void tune_save(const char *path);
 void tune_load(const char *path);
 
+// The graphs of a disjoint union: graph c owns lower ids [l_off[c],
+// l_off[c+1]) and upper ids n_lower + [u_off[c], u_off[c+1]) (device arrays
+// of n + 1 entries).
+struct Components {
+    int32_t n = 0;
+    const int64_t *l_off = nullptr;
+    const int64_t *u_off = nullptr;
+};
+
 struct RankCSR {
     TuneParams tp;
     int32_t n_lower = 0, n = 0;
@@ -54,6 +63,9 @@ struct RankCSR {
     int64_t *wpre = nullptr;  // [2m + 1] exclusive prefix of rev: wedge work
     int64_t wedges_po = 0;    // priority-obeyed wedges (host copy)
     int32_t max_deg = 0;
+    // Unions only: the first rank of x's graph in x's layer (end vertices of
+    // x's wedges lie in [zbase[x], x)); null for a single graph.
+    int32_t *zbase = nullptr;
 };
 
 // Work items of the wedge sweeps.
@@ -98,7 +110,11 @@ int64_t bitruss_components(const bt_csr &g, const int64_t *phi, int64_t k, int32
 
 // Validates the CSR and builds the rank-space adjacency in `ws`.
 // Throws Error{BT_EINVAL} for malformed input.
-void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s);
+// `comps` (nullable): g is a disjoint union of these graphs; the rank order
+// then puts each graph's vertices together within a layer (the order
+// restricted to a graph is unchanged).
+void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s,
+             const Components *comps = nullptr);
 
 // Splits start vertices into wedge tasks (sync point: reads counts).
 void make_tasks(const RankCSR &r, TaskLists &t, Workspace &ws, hipStream_t s);
