@@ -500,6 +500,24 @@ void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
 
 }  // namespace bt
 
+namespace {
+
+// Launch parameters across the C ABI.
+bt::TuneParams from_c(const bt_tune_params &p) {
+    bt::TuneParams t;
+    t.hash_max_work = p.hash_max_work;
+    t.dense_chunk = p.dense_chunk;
+    t.wedge_wg_per_cu = p.wedge_wg_per_cu;
+    t.peel_blocks = p.peel_blocks;
+    t.active_min = p.active_min;
+    return t;
+}
+bt_tune_params to_c(const bt::TuneParams &t) {
+    return bt_tune_params{t.hash_max_work, t.dense_chunk, t.wedge_wg_per_cu, t.peel_blocks,
+                          t.active_min};
+}
+}  // namespace
+
 using namespace bt;
 
 struct bt_index {
@@ -644,21 +662,6 @@ bt_status bt_decompose_variant(const bt_csr *g, int32_t variant, int64_t *sup_ou
     });
 }
 
-namespace {
-bt::TuneParams from_c(const bt_tune_params &p) {
-    bt::TuneParams t;
-    t.hash_max_work = p.hash_max_work;
-    t.dense_chunk = p.dense_chunk;
-    t.wedge_wg_per_cu = p.wedge_wg_per_cu;
-    t.peel_blocks = p.peel_blocks;
-    t.active_min = p.active_min;
-    return t;
-}
-bt_tune_params to_c(const bt::TuneParams &t) {
-    return bt_tune_params{t.hash_max_work, t.dense_chunk, t.wedge_wg_per_cu, t.peel_blocks,
-                          t.active_min};
-}
-}  // namespace
 
 bt_status bt_tune(const bt_csr *gs, int32_t n_graphs, uint32_t what, bt_tune_params *out,
                   hipStream_t stream) {

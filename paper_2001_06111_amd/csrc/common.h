@@ -129,11 +129,12 @@ __device__ __forceinline__ T block_exclusive_sum(T v, T *scratch, T *total) {
     T inc = wave_inclusive_sum(v);
     if (lane_id() == kWave - 1) scratch[w] = inc;
     __syncthreads();
-    if (threadIdx.x < kWave) {
-        T s = threadIdx.x < nw ? scratch[threadIdx.x] : T(0);
+    const int t = (int)threadIdx.x;
+    if (t < kWave) {
+        T s = t < nw ? scratch[t] : T(0);
         T si = wave_inclusive_sum(s);
-        if (threadIdx.x < nw) scratch[threadIdx.x] = si - s;
-        if (threadIdx.x == nw - 1) scratch[nw] = si;
+        if (t < nw) scratch[t] = si - s;
+        if (t == nw - 1) scratch[nw] = si;
     }
     __syncthreads();
     T r = scratch[w] + inc - v;

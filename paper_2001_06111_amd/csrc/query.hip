@@ -63,8 +63,8 @@ __global__ void k_cc_hook(const int64_t *row_ptr, const int32_t *col, int32_t nu
     }
 }
 
-__global__ void k_cc_min_edge(const int64_t *row_ptr, const int32_t *col, int32_t nu, int32_t nl,
-                              const int64_t *phi, int64_t k, int32_t *parent, int32_t *min_edge) {
+__global__ void k_cc_min_edge(const int64_t *row_ptr, int32_t nu, int32_t nl, const int64_t *phi,
+                              int64_t k, int32_t *parent, int32_t *min_edge) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < nu;
          i += waves)
@@ -114,7 +114,7 @@ int64_t bitruss_components(const bt_csr &g, const int64_t *phi, int64_t k, int32
     fill_i32(min_edge, INT_MAX, n, s);
     k_cc_hook<<<grid_r, kB, 0, s>>>(g.row_ptr, g.col, nu, nl, phi, k, parent);
     BT_CHECK_LAUNCH();
-    k_cc_min_edge<<<grid_r, kB, 0, s>>>(g.row_ptr, g.col, nu, nl, phi, k, parent, min_edge);
+    k_cc_min_edge<<<grid_r, kB, 0, s>>>(g.row_ptr, nu, nl, phi, k, parent, min_edge);
     BT_CHECK_LAUNCH();
     k_cc_first<<<grid_r, kB, 0, s>>>(g.row_ptr, nu, nl, phi, k, parent, min_edge, first);
     BT_CHECK_LAUNCH();
