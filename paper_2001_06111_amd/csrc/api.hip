@@ -480,7 +480,7 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
 
 // Batches are cut at about kBatchEdges edges so that each union stays well
 // inside the index limits; an oversized union is split in halves.
-constexpr int64_t kBatchEdges = int64_t(1) << 25;
+constexpr int64_t kBatchEdges = int64_t(1) << 26;
 
 }  // namespace
 
