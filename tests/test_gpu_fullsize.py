@@ -78,3 +78,26 @@ def test_pool512_batched_digests():
     assert hp.hexdigest() == want["phi_sha256"]
     for i, g in enumerate(want["per_graph"]):
         assert sha(phis[i].cpu().numpy()) == g["phi_sha256"]
+
+
+def test_request_graph_2m_digest():
+    """The first 2M-edge graph of the request stream (the serving workload's
+    large class), decomposed alone and through the serving engine: supports
+    and bitruss numbers equal the oracle's, bit for bit."""
+    want = GOLD["big:1"]
+    assert want["generator_version"] == synth.GENERATOR_VERSION
+    g = synth.big_serving_graph(0)
+    dg = binding.DeviceGraph.upload(g)
+    sup, phi, st = binding.bt_decompose(dg, stats=True)
+    assert st["butterflies"] == want["butterflies"]
+    assert sha(sup.cpu().numpy()) == want["sup_sha256"]
+    assert sha(phi.cpu().numpy()) == want["phi_sha256"]
+    eng = binding.BtEngine()
+    try:
+        eng.bt_engine_submit(dg, 7)
+        eng.bt_engine_drain()
+        assert eng.bt_engine_poll() == [(7, binding.BT_OK)]
+        status, _, phi_e = eng.results[7]
+        assert sha(phi_e.cpu().numpy()) == want["phi_sha256"]
+    finally:
+        eng.bt_engine_destroy()
