@@ -5,10 +5,11 @@
 // stream and a workspace; when a slot is free it admits, in arrival order,
 // queued requests of the class of the oldest one while their estimates fit
 // the engine's memory budget (less what the other slots hold), and
-// decomposes them together as one disjoint union.  A large request (at
-// least kLargeEdges edges) runs alone; small requests are batched together
-// and passed over large ones, so they do not wait for a large request's
-// peel.  Requests that arrive while batches run are admitted by the next
+// decomposes them together as one disjoint union.  Large requests (at
+// least kLargeEdges edges) are batched only with large ones, a few at a
+// time, small requests only with small ones, so a small request never waits
+// for a large graph's peel inside its batch.  Small batches go first unless
+// the oldest large request has waited kLargeWaitS.  Requests that arrive while batches run are admitted by the next
 // free slot, so batches on different slots overlap on the GPU.  Each result
 // equals the plain single-graph decomposition of the request.
 #include <chrono>
@@ -30,6 +31,7 @@ struct Request {
     int64_t *phi;
     uint64_t id;
     int64_t bytes;
+    std::chrono::steady_clock::time_point t;  // submit time
 };
 
 struct Done {
@@ -38,6 +40,14 @@ struct Done {
 };
 
 constexpr int64_t kLargeEdges = int64_t(1) << 19;
+// Large requests share a batch too (one union, one shared level, so their
+// rounds overlap: four 2M-edge graphs take 1.7x less time together than one
+// after another), but at most this many, to bound each one's latency.
+constexpr int32_t kLargePerBatch = 4;
+// Small batches go first (they take a fraction of a large batch's time),
+// unless the oldest large request has waited this long (so a steady stream
+// of small requests cannot starve large ones).
+constexpr double kLargeWaitS = 10.0;
 
 }  // namespace
 }  // namespace bt
@@ -63,7 +73,25 @@ struct bt_engine {
     int64_t batches = 0, admitted = 0;
 
     void worker_loop(int slot);
+    bool pick_large() const;
+    const Request *first_of(bool large) const;
 };
+
+const Request *bt_engine::first_of(bool large) const {
+    for (const Request &r : queue)
+        if ((r.g.m >= kLargeEdges) == large) return &r;
+    return nullptr;
+}
+
+// The class of the next batch (call with mu held).
+bool bt_engine::pick_large() const {
+    const Request *l = first_of(true);
+    if (!l) return false;
+    if (!first_of(false)) return true;
+    const double waited =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - l->t).count();
+    return waited >= kLargeWaitS;
+}
 
 void bt_engine::worker_loop(int slot) {
     (void)hipSetDevice(device);
@@ -76,15 +104,18 @@ void bt_engine::worker_loop(int slot) {
         int64_t bytes = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
+            bool large = false;
             cv_work.wait(lk, [&] {
                 if (stop) return true;
-                return !queue.empty() && reserved + queue.front().bytes <= budget;
+                if (queue.empty()) return false;
+                large = pick_large();
+                return reserved + first_of(large)->bytes <= budget;
             });
             if (stop) break;  // destroy drains the queue before it stops workers
-            // The oldest request fixes the class; admit requests of that class
-            // in arrival order while the budget allows (a large one alone).
-            const bool large = queue.front().g.m >= kLargeEdges;
-            for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < max_batch;) {
+            // Admit requests of the chosen class in arrival order while the
+            // budget allows.
+            const int32_t cap = large ? std::min(max_batch, kLargePerBatch) : max_batch;
+            for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < cap;) {
                 if ((it->g.m >= kLargeEdges) != large) {
                     ++it;
                     continue;
@@ -93,7 +124,6 @@ void bt_engine::worker_loop(int slot) {
                 bytes += it->bytes;
                 batch.push_back(*it);
                 it = queue.erase(it);
-                if (large) break;
             }
             reserved += bytes;
             running += (int64_t)batch.size();
@@ -198,6 +228,7 @@ bt_status bt_engine_submit(bt_engine *E, const bt_csr *g, int64_t *sup_out, int6
     r.sup = sup_out;
     r.phi = phi_out;
     r.id = id;
+    r.t = std::chrono::steady_clock::now();
     {
         std::lock_guard<std::mutex> lk(E->mu);
         E->queue.push_back(r);

@@ -210,15 +210,16 @@ def test_engine_alone_equals_mix():
 
 
 def test_engine_size_classes():
-    """A large request (2^19+ edges) runs alone while small ones are batched past
-    it; every result still equals the plain decomposition."""
-    big = synth.scaled_chunglu(600_000, seed=6)
-    assert big.m >= 1 << 19
-    gs = [synth.batch_graph(i) for i in range(3)] + [big] + [synth.batch_graph(i)
-                                                           for i in range(3, 9)]
+    """Large requests (2^19+ edges) are batched only with each other while
+    small ones are batched past them; every result still equals the plain
+    decomposition."""
+    big = [synth.scaled_chunglu(600_000, seed=6), synth.scaled_chunglu(550_000, seed=8)]
+    assert all(b.m >= 1 << 19 for b in big)
+    gs = ([synth.batch_graph(i) for i in range(3)] + big[:1] + [synth.batch_graph(i)
+                                                                for i in range(3, 9)] + big[1:])
     mix, done, stats = _run_engine(gs, slots=1, stagger=0.001)
     assert sorted(i for i, _ in done) == list(range(len(gs)))
-    assert stats["batches"] >= 2  # the large request never shares a batch
+    assert stats["batches"] >= 2  # the classes never share a batch
     for i, g in enumerate(gs):
         s, sup, phi = mix[i]
         assert s == binding.BT_OK
