@@ -2,7 +2,15 @@
 
 One step = one full bt_decompose (validation, priority order, rank-space
 CSR, wedge counting, BE-Index construction, peel) of the 5M-edge Chung-Lu
-graph, with the input CSR already resident in HBM.  Prints one JSON line.
+graph, with the input CSR already resident in HBM.  Prints one JSON line:
+the timed steps (value, ms_per_step, p50/p99 step times), the peel kernel
+against the HBM roofline and its measured HBM traffic, its atomic
+throughput, and, outside the timed steps: launch parameters picked by the
+autotuner (--tune), the same peel without batch bloom processing
+(--ablation), batched against plain graphs/s on 256 pool graphs (--batch)
+and on the whole 4,096-graph pool (--batch-all), served against plain FIFO
+latency on a burst of requests (--serve), and the CPU oracle on a sample
+(cpu_baseline).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
