@@ -79,3 +79,22 @@ def test_bad_files_change_nothing(tmp_path, text):
 def test_missing_file():
     with pytest.raises(binding.BtError):
         binding.bt_tune_load(os.path.join("/nonexistent", "tune.txt"))
+
+
+def test_cache_file_from_environment(tmp_path):
+    """BT_TUNE_CACHE names a file that the library loads at its first lookup."""
+    import subprocess
+    import sys
+    f = tmp_path / "tune.txt"
+    f.write_text("bt-tune 1 unknown\nsingle 13 1024 4096 1 128 4096\n")
+    code = ("import json; from paper_2001_06111_amd import binding; "
+            "print(json.dumps(binding.bt_tune_get(5_000_000)))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, BT_TUNE_CACHE=str(f), PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=120, cwd=root)
+    assert out.returncode == 0, out.stderr
+    import json
+    assert json.loads(out.stdout.strip().splitlines()[-1]) == {
+        "hash_max_work": 1024, "dense_chunk": 4096, "wedge_wg_per_cu": 1, "peel_blocks": 128,
+        "active_min": 4096}
