@@ -76,7 +76,7 @@ def main():
                     help="also run a 256 MiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library decomposes on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
