@@ -122,6 +122,7 @@ void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
     BT_HIP(hipMemsetAsync(ix.cursor, 0, sizeof(uint64_t) * 2, s));
     build_index(r, t, ix, ws, s);
     if (ev) ev->mark(2);
+    check_butterfly_total(ix.supl, r.m, ix.butterflies, ws, s);
     int64_t *hs = ws.host(4);
     BT_HIP(hipMemcpyAsync(hs, ix.cursor, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
@@ -212,6 +213,7 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
     BT_HIP(hipMemsetAsync(supl, 0, sizeof(uint64_t) * (m + 1), s));
     BT_HIP(hipMemsetAsync(bf, 0, sizeof(int64_t) * 2, s));
     count_support(r, t, supl, bf, s);
+    check_butterfly_total(supl, m, bf, ws, s);
     if (sup_out && m) supl_to_sup(supl, sup_out, m, s);
     int32_t *sup0 = ws.get<int32_t>("pc_sup0", m);
     const int32_t kmax = pc_kmax(supl, m, sup0, ws, s);
@@ -556,6 +558,7 @@ bt_status bt_support(const bt_csr *g, int64_t *sup_out, int64_t *butterflies_out
         BT_HIP(hipMemsetAsync(supl, 0, sizeof(uint64_t) * (g->m + 1), stream));
         BT_HIP(hipMemsetAsync(bf, 0, sizeof(int64_t) * 2, stream));
         count_support(r, t, supl, bf, stream);
+        check_butterfly_total(supl, g->m, bf, ws, stream);
         supl_to_sup(supl, sup_out, g->m, stream);
         int64_t *hs = ws.host(2);
         BT_HIP(hipMemcpyAsync(hs, bf, sizeof(int64_t), hipMemcpyDeviceToHost, stream));

@@ -196,5 +196,10 @@ int64_t footprint_bytes(const bt_csr &g, Workspace &ws, hipStream_t s);
 
 // supl low halves to int64 supports.
 void supl_to_sup(const uint64_t *supl, int64_t *sup, int64_t m, hipStream_t s);
+// The butterfly total two ways (Lemma 1: every butterfly has four edges;
+// Lemma 8: a k-bloom holds C(k, 2)): the supports must sum to four times the
+// blooms' total, else BT_EDEVICE.
+void check_butterfly_total(const uint64_t *supl, int64_t m, const int64_t *butterflies,
+                           Workspace &ws, hipStream_t s);
 
 }  // namespace bt

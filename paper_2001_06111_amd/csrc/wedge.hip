@@ -279,6 +279,16 @@ __global__ void k_supl_to_sup(const uint64_t *supl, int64_t *sup, int64_t m) {
         sup[e] = (int64_t)(supl[e] & 0xffffffffu);
 }
 
+// Sum of the supports (low halves of the packed words).
+__global__ void k_support_total(const uint64_t *supl, int64_t m, unsigned long long *out) {
+    unsigned long long acc = 0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x)
+        acc += supl[e] & 0xffffffffu;
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+
 __global__ void k_link_counts(const uint64_t *supl, int64_t m, int32_t *cnt) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x)
@@ -341,6 +351,23 @@ void supl_to_sup(const uint64_t *supl, int64_t *sup, int64_t m, hipStream_t s) {
     if (m <= 0) return;
     k_supl_to_sup<<<grid_for(m, 256, 16384), 256, 0, s>>>(supl, sup, m);
     BT_CHECK_LAUNCH();
+}
+
+void check_butterfly_total(const uint64_t *supl, int64_t m, const int64_t *butterflies,
+                           Workspace &ws, hipStream_t s) {
+    if (m <= 0) return;
+    unsigned long long *tot = ws.get<unsigned long long>("bf_check", 1);
+    BT_HIP(hipMemsetAsync(tot, 0, sizeof *tot, s));
+    k_support_total<<<grid_for(m, 256, 4096), 256, 0, s>>>(supl, m, tot);
+    BT_CHECK_LAUNCH();
+    int64_t *h = ws.host(2);
+    BT_HIP(hipMemcpyAsync(h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipMemcpyAsync(h + 1, butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BT_HIP(hipStreamSynchronize(s));
+    if (h[0] != 4 * h[1])
+        throw Error{BT_EDEVICE, "butterfly totals disagree: supports sum to " +
+                                    std::to_string(h[0]) + ", blooms give 4 x " +
+                                    std::to_string(h[1])};
 }
 
 void count_support(const RankCSR &r, const TaskLists &t, uint64_t *supl, int64_t *bf,
