@@ -37,10 +37,15 @@
 // together, small rounds spread over many CUs.
 // The active set holds the remaining edges with support below a threshold T
 // (a decrement that crosses T appends the edge).  When no active edge
-// remains the device raises `stall` and the host rebuilds the set with a
-// larger T from a histogram of the remaining supports.  Lists that one
-// round fills and the next consumes are double-buffered by round parity;
-// every counter is reset in a phase that does not read it.
+// remains, the persistent kernel rebuilds the set itself with a larger T
+// from a histogram of the remaining supports (in the two-kernel form the
+// device raises `stall` and the host rebuilds it), so one launch peels the
+// whole graph.  Lists that one round fills and the next consumes are
+// double-buffered by round parity; every counter is reset in a phase that
+// does not read it.
+// An ablation mode (`unit`) drops batch bloom processing: each survivor
+// takes C[B] decrements of one instead of one decrement of C[B].
+// Batches of graphs peel in k_peel_multi, each graph at its own level.
 #include <algorithm>
 #include <climits>
 #include <cstdio>
