@@ -381,11 +381,12 @@ def measured_traffic(launches):
 
     profiles/peel_chunglu5m_traffic.md records FETCH_SIZE and WRITE_SIZE of
     the peel kernel, scaled by what the counters read for a copy of known
-    size, together with the SHA-256 of the peel source they were taken on.
-    Returns None when the source has changed since (or no summary exists).
+    size, together with the SHA-256 of the peel source they were taken on
+    (peel.hip followed by peel_common.h).  Returns None when the source has
+    changed since (or no summary exists).
     """
     path = os.path.join(ROOT, "profiles", "peel_chunglu5m_traffic.md")
-    src = os.path.join(ROOT, "paper_2001_06111_amd", "csrc", "peel.hip")
+    csrc = os.path.join(ROOT, "paper_2001_06111_amd", "csrc")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -393,7 +394,10 @@ def measured_traffic(launches):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip()
-    want = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in ("peel.hip", "peel_common.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    want = h.hexdigest()
     if fields.get("peel_source_sha256") != want or "hbm_bytes_total" not in fields:
         return None
     return float(fields["hbm_bytes_total"]) / launches

@@ -46,234 +46,16 @@
 // An ablation mode (`unit`) drops batch bloom processing: each survivor
 // takes C[B] decrements of one instead of one decrement of C[B].
 // Batches of graphs peel in k_peel_multi, each graph at its own level.
-#include <algorithm>
-#include <climits>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <mutex>
-#include <vector>
-
-#include "pipeline.h"
+#include "peel_common.h"
 
 namespace bt {
 
-namespace {
-
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kLinkChunk = kWave;   // links per phase-A work item (one per lane)
-// Progressive mode: edge ids in wedge records and link twins carry this bit
-// when the edge's bitruss number was fixed in an earlier pass; such edges
-// keep their blooms alive but are never decremented or removed.
-constexpr uint32_t kFixedBit = 0x80000000u;
-constexpr uint32_t kEdgeMask = 0x7fffffffu;
-constexpr int kWedgeChunk = kWave;  // wedges per phase-B work item (one per lane)
-int grid_a() {
-    static int g = std::getenv("BT_PEEL_GRID_A") ? std::atoi(std::getenv("BT_PEEL_GRID_A")) : 2048;
-    return g;
-}
-int grid_b() {
-    static int g = std::getenv("BT_PEEL_GRID_B") ? std::atoi(std::getenv("BT_PEEL_GRID_B")) : 2048;
-    return g;
-}
-
-typedef unsigned long long u64;
-
-// Cooperative peel kernels hold every CU until their last round; two of
-// them at once (from different threads or engine slots) could each wait at
-// a grid barrier for blocks the other keeps from being scheduled.  They
-// therefore run one at a time in the process.
 std::mutex &coop_mutex() {
     static std::mutex *m = new std::mutex();  // never destroyed: outlives static teardown
     return *m;
 }
 
-enum : int32_t { kNormal = 0, kGather = 1 };
-
-// A counter alone on its cache line (contended atomics do not share lines).
-struct alignas(128) Counter {
-    u64 v;
-};
-
-struct PeelCtl {
-    Counter nf[2];      // frontier work items by round parity
-    Counter ntc[2];     // bloom work items by round parity
-    Counter na[2];      // active-set entries by buffer
-    Counter updates;
-    Counter bloom_visits;
-    Counter unbatched;  // extra decrements if survivors took one per kill (no bloom batching)
-    // Round state, indexed by round parity.  Round r's entry is derived
-    // from round r - 1's final counters (every block computes the same
-    // values; block 0 stores them for round r + 1).
-    int32_t mode[2];    // kNormal or kGather
-    int32_t level[2];
-    int32_t cur[2];     // active-set buffer in use
-    int32_t gmin[2];    // gather rounds: minimum support above the level
-    int32_t stall;
-    int32_t thresh;     // active threshold T
-    int32_t max_level;  // largest level at which edges were removed
-    int32_t pad;        // persistent kernel: parity of the next round
-    u64 rounds, levels;
-    u64 prof[6];        // persistent kernel, BT_PEEL_PROFILE=1: block-0 clock ticks
-    // BT_PEEL_PROFILE=1: frontier pushes by twin (phase A) and survivor
-    // (phase B) decrements, by list parity; rounds whose frontier came from
-    // twin decrements alone; log2 histograms of per-round work items.
-    Counter push_twin[2], push_surv[2];
-    u64 twin_only_rounds, twin_pushes, surv_pushes;
-    u64 hist_nf[32], hist_ntc[32];
-};
-
-struct alignas(16) FrontItem {
-    int32_t e;
-    int32_t level;    // level of the round that removes e
-    uint32_t lo, hi;  // link positions of this chunk
-};
-
-struct alignas(16) BloomItem {
-    int32_t b;
-    int32_t nch;    // chunks of this bloom (the last one to finish finalizes)
-    uint32_t lo, hi;  // wedge range of this chunk
-};
-
-struct PeelArgs {
-    PeelCtl *ctl;
-    int32_t *sup;
-    int32_t *phi;
-    uint32_t *alive;
-    int32_t *bc;
-    int32_t *bk;
-    int32_t *bdone;
-    const uint32_t *bwoff;
-    const int32_t *wea;
-    const int32_t *web;
-    const int32_t *wbl;
-    const int64_t *link_off;
-    const uint3 *link;  // {wedge, bloom, twin edge}
-    int32_t prof;       // count profile statistics
-    int32_t unit;       // ablation without batch bloom processing (BiT-BU+)
-    FrontItem *front[2];
-    BloomItem *tc[2];
-    int32_t *act[2];
-};
-
-// Coherent access to state that blocks share within one launch.  The eight
-// XCDs keep separate L2 caches; device-scope loads and stores (relaxed
-// atomics) go to the point of coherence, so no round needs the L2 write-back
-// and invalidation that a device-scope fence costs, and the read-only index
-// stays cached in L2 across rounds.  Every access to mutable peel state
-// inside a launch goes through these.
-template <typename T> __device__ __forceinline__ T ld(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T> __device__ __forceinline__ void st(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// 16-byte work items move as two coherent 8-byte halves.
-template <typename Item> __device__ __forceinline__ void st_item(Item *p, const Item &v) {
-    static_assert(sizeof(Item) == 16, "work items are 16 bytes");
-    u64 h[2];
-    __builtin_memcpy(h, &v, 16);
-    st(reinterpret_cast<u64 *>(p), h[0]);
-    st(reinterpret_cast<u64 *>(p) + 1, h[1]);
-}
-template <typename Item> __device__ __forceinline__ Item ld_item(const Item *p) {
-    u64 h[2];
-    h[0] = ld(reinterpret_cast<const u64 *>(p));
-    h[1] = ld(reinterpret_cast<const u64 *>(p) + 1);
-    Item v;
-    __builtin_memcpy(&v, h, 16);
-    return v;
-}
-
-// Each lane asks for `cnt` consecutive slots of *counter; one atomic per
-// wave.  Must be called by all 64 lanes.
-__device__ __forceinline__ u64 wave_alloc(uint32_t cnt, u64 *counter) {
-    const u64 inc = wave_inclusive_sum<u64>((u64)cnt);
-    const u64 total = __shfl(inc, kWave - 1, kWave);
-    u64 base = 0;
-    if (lane_id() == kWave - 1 && total) base = atomicAdd(counter, total);
-    base = __shfl(base, kWave - 1, kWave);
-    return base + inc - cnt;
-}
-
-// Slot requests against up to three counters (a null counter takes no
-// requests): each wave issues its atomics together and waits once.  Must be
-// called by all 64 lanes.
-__device__ __forceinline__ void wave_alloc3(uint32_t c0, u64 *k0, uint32_t c1, u64 *k1,
-                                            uint32_t c2, u64 *k2, u64 (&base)[3]) {
-    const uint32_t cnt[3] = {c0, c1, c2};
-    u64 *const ctr[3] = {k0, k1, k2};
-    uint32_t inc[3], tot[3];  // a wave's requests stay far below 2^32
-    u64 r[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        inc[k] = wave_inclusive_sum<uint32_t>(cnt[k]);
-        tot[k] = __shfl(inc[k], kWave - 1, kWave);
-    }
-    if (lane_id() == kWave - 1) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            if (tot[k]) r[k] = atomicAdd(ctr[k], (u64)tot[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) base[k] = __shfl(r[k], kWave - 1, kWave) + (inc[k] - cnt[k]);
-}
-
-// Frontier work items of an edge: its links in chunks of 64, at least one
-// chunk so that an edge without links still receives its bitruss number.
-__device__ __forceinline__ uint32_t link_chunks(uint32_t lo, uint32_t hi) {
-    return hi - lo <= (uint32_t)kLinkChunk ? 1u : (hi - lo + kLinkChunk - 1) / kLinkChunk;
-}
-
-// The pusher also records the edge's bitruss number: an edge is queued at
-// the level of the round that removes it (a queued frontier keeps the
-// level), and only a gather, which runs once the frontier is empty, reads
-// phi while the peel runs.
-// Writes the cnt 64-element chunks of a lane's range [lo, hi) as items
-// {id, aux, a, min(a + 64, hi)} at slots base, base + 1, ...  A lane writes
-// up to kOwnChunks of its own; the rest of a longer range is written by the
-// whole wave, 64 chunks at a time, so a hub edge or a large bloom does not
-// hold up its wave (and the round) with thousands of serial stores.  All 64
-// lanes must call.
-constexpr uint32_t kOwnChunks = 4;
-template <typename Item>
-__device__ __forceinline__ void put_chunks(Item *list, u64 base, uint32_t cnt, int32_t id,
-                                           int32_t aux, uint32_t lo, uint32_t hi) {
-    const uint32_t own = min(cnt, kOwnChunks);
-    for (uint32_t c = 0; c < own; ++c) {
-        const uint32_t a = lo + c * kWave;
-        st_item(&list[base + c], Item{id, aux, a, min(a + (uint32_t)kWave, hi)});
-    }
-    unsigned long long big = __ballot(cnt > own);
-    while (big) {
-        const int l = __ffsll(big) - 1;
-        big &= big - 1;
-        const uint32_t n = __shfl(cnt, l, kWave);
-        const u64 b = __shfl(base, l, kWave);
-        const int32_t lid = __shfl(id, l, kWave), laux = __shfl(aux, l, kWave);
-        const uint32_t llo = __shfl(lo, l, kWave), lhi = __shfl(hi, l, kWave);
-        for (uint32_t c = kOwnChunks + lane_id(); c < n; c += kWave) {
-            const uint32_t a = llo + c * kWave;
-            st_item(&list[b + c], Item{lid, laux, a, min(a + (uint32_t)kWave, lhi)});
-        }
-    }
-}
-
-__device__ __forceinline__ void put_front(const PeelArgs &P, int q, u64 base, int32_t e,
-                                          uint32_t lo, uint32_t hi, uint32_t k, int32_t level) {
-    if (k) st(&P.phi[e], level);
-    put_chunks(P.front[q], base, k, e, level, lo, hi);  // the item carries the level
-}
-
-enum : int { kSrcTwin = 0, kSrcSurvivor = 1 };
-
-// Profile statistics: frontier pushes by the decrement that caused them.
-__device__ __forceinline__ void count_push(const PeelArgs &P, int q, int src, uint32_t n) {
-    const u64 t = wave_sum<u64>((u64)n);
-    if (lane_id() == 0 && t)
-        atomicAdd(src == kSrcTwin ? &P.ctl->push_twin[q].v : &P.ctl->push_surv[q].v, t);
-}
+namespace {
 
 // Round parameters.  One thread per block reads them from the control block
 // after each barrier and hands them to the block through LDS, so the
@@ -656,60 +438,6 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
     flush_stats(C, upd, visits, unb);
 }
 
-// --- persistent cooperative kernel: rounds separated by grid barriers ---
-
-constexpr int kPBlock = 1024;  // 16 waves per CU (up to 128 VGPRs: four waves per SIMD)
-
-struct GridBar {
-    Counter group[8];  // arrivals per group (monotonic)
-    Counter top;       // completed groups (monotonic)
-    Counter rel[8];    // per-group release: the number of the last open barrier
-    int32_t fail;
-};
-
-// Waits until this wave's memory operations have completed: its device-scope
-// stores and atomics have reached the point of coherence.
-__device__ __forceinline__ void drain_memory() {
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// Two-level barrier, thread 0 of each block; `k` counts the barriers this
-// block has passed.  Blocks arrive at one of eight group counters (group g
-// holds the blocks of XCD g), the last of each group at the top counter; the
-// last of those writes the barrier's number to every group's release word,
-// and each block polls its own group's word, so no address takes the polls
-// of the whole grid.  Counters only grow, so nothing is reset between
-// barriers.  Shared state is only touched through device-scope accesses, so
-// draining every wave's outstanding operations before arrival (done by the
-// caller for all waves) orders them before the barrier, with no cache
-// write-back or invalidation.  A waiter gives up after a bounded spin (the
-// kernel then stops with `fail` set) so no bug can hang the device.
-__device__ bool grid_arrive_wait(GridBar *B, u64 &k) {
-    const unsigned nb = gridDim.x;
-    const unsigned g = blockIdx.x & 7;
-    const unsigned ngroups = nb < 8 ? nb : 8;
-    const unsigned gsize = (nb - g + 7) / 8;
-    k += 1;
-    if (atomicAdd(&B->group[g].v, 1ull) == k * gsize - 1) {
-        if (atomicAdd(&B->top.v, 1ull) == k * ngroups - 1) {
-            for (unsigned j = 0; j < ngroups; ++j) st(&B->rel[j].v, k);
-        }
-    }
-    bool ok = true;
-    int64_t spins = 0;
-    while (ld(&B->rel[g].v) < k) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (int64_t(1) << 28) || ld(&B->fail)) {
-            st(&B->fail, 1);
-            ok = false;
-            break;
-        }
-    }
-    drain_memory();
-    return ok;
-}
-
 // Rebuild of the active set inside the persistent kernel, when it has run
 // dry: the remaining edges (phi < 0) are compacted from one list into the
 // other while their minimum support mn is found; a log2 histogram of
@@ -977,396 +705,6 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     }
 }
 
-// --- grid-wide peel of many graphs, each at its own level ------------------
-//
-// A batch is a disjoint union, but its graphs need not share levels: here
-// every graph has its own state (level, whether it has frontier work, the
-// result of its last gather) and the grid advances all of them in each
-// round.  Work items carry their graph's level, so the crossing test needs
-// no lookup.  A graph's level change is decided at the start of a round from
-// what the previous round left (a frontier for this round, or the result of
-// its gather) and, when needed, a gather over the graph's edges is scheduled
-// for the next round: per level a graph spends its normal rounds, one idle
-// round and one gather round.  A gather rescans the graph's whole edge range
-// (no active set): batch graphs are small, and the scan is coalesced.
-
-enum : int32_t { kGsNormal = 0, kGsDone = 1 };
-constexpr int kGatherPerLane = 8;  // edges per lane of a gather item
-constexpr uint32_t kGatherChunk = kWave * kGatherPerLane;
-
-struct alignas(64) GState {
-    int32_t state;      // kGsNormal or kGsDone
-    int32_t level;
-    int32_t gmin[2];    // minimum remaining support above the level, by round parity
-    int32_t fr[2];      // frontier items exist for the round of this parity
-    int32_t e0, e1;     // edge range in the union
-    int64_t gather_round;  // round of the last scheduled gather (-1: none)
-    int32_t levels;        // levels this graph visited
-    int32_t max_level;
-};
-
-struct alignas(16) MBloomItem {
-    int32_t b;
-    int32_t level;
-    uint32_t lo;
-    uint32_t meta;  // (chunks of the bloom << 7) | (wedges in this chunk)
-};
-
-struct alignas(16) GatherItem {
-    int32_t g;
-    int32_t level;
-    uint32_t lo, hi;  // positions in the graph's current remaining list
-};
-
-struct MultiCtl {
-    Counter nf[2], ntc[2], ngth[2];
-    Counter updates, bloom_visits;
-    Counter left;  // graphs not done
-    u64 rounds;
-    u64 prof[5];   // BT_PEEL_PROFILE=1: block-0 clock ticks (decide, A, bar, B, bar)
-};
-
-struct MultiArgs {
-    MultiCtl *ctl;
-    GState *gs;
-    const int32_t *gid;  // graph of each edge
-    int32_t ng;
-    FrontItem *front[2];
-    MBloomItem *tc[2];
-    GatherItem *gth[2];
-};
-
-__device__ __forceinline__ void set_front_flag(const MultiArgs &M, int32_t g, int q) {
-    st(&M.gs[g].fr[q], 1);
-}
-
-// Bloom items of the lanes' first kills, written cooperatively (as put_chunks).
-__device__ __forceinline__ void put_bloom_items(MBloomItem *list, u64 base, uint32_t cnt,
-                                                int32_t b, int32_t level, uint32_t lo,
-                                                uint32_t hi) {
-    const uint32_t own = min(cnt, kOwnChunks);
-    for (uint32_t c = 0; c < own; ++c) {
-        const uint32_t a = lo + c * kWave;
-        st_item(&list[base + c], MBloomItem{b, level, a, (cnt << 7) | (min(a + (uint32_t)kWave, hi) - a)});
-    }
-    unsigned long long big = __ballot(cnt > own);
-    while (big) {
-        const int l = __ffsll(big) - 1;
-        big &= big - 1;
-        const uint32_t n = __shfl(cnt, l, kWave);
-        const u64 bb = __shfl(base, l, kWave);
-        const int32_t lb = __shfl(b, l, kWave), ll = __shfl(level, l, kWave);
-        const uint32_t llo = __shfl(lo, l, kWave), lhi = __shfl(hi, l, kWave);
-        for (uint32_t c = kOwnChunks + lane_id(); c < n; c += kWave) {
-            const uint32_t a = llo + c * kWave;
-            st_item(&list[bb + c], MBloomItem{lb, ll, a, (n << 7) | (min(a + (uint32_t)kWave, lhi) - a)});
-        }
-    }
-}
-
-// Decides, at the start of round r (parity p), what each of this thread's
-// graphs does next; schedules gathers for round r + 1 into gth[q].  All
-// state reads are issued together.
-__device__ void multi_decide(const MultiArgs &M, int64_t r, int p, int64_t tid, int64_t nthreads) {
-    const int q = p ^ 1;
-    for (int64_t g0 = tid - lane_id(); g0 < M.ng; g0 += nthreads) {
-        const int64_t g = g0 + lane_id();
-        bool sched = false;
-        int32_t lvl = 0, e0 = 0, e1 = 0;
-        if (g < M.ng) {
-            GState *G = &M.gs[g];
-            const int32_t state = ld(&G->state);
-            const int64_t gr = ld(&G->gather_round);
-            const int32_t fr = ld(&G->fr[p]);
-            const int32_t level = ld(&G->level);
-            const int32_t gm = ld(&G->gmin[q]);
-            e0 = ld(&G->e0);
-            e1 = ld(&G->e1);
-            if (state != kGsDone) {
-                if (fr) st(&G->fr[p], 0);
-                if (gr != r && !fr) {
-                    // No frontier this round: the level is exhausted.  After a
-                    // gather that took nothing, jump to the smallest remaining
-                    // support, or finish when nothing remains.
-                    int32_t next = level + 1;
-                    if (gr == r - 1) {
-                        next = gm;
-                        if (gm == INT_MAX) {
-                            st(&G->state, (int32_t)kGsDone);
-                            atomicAdd(&M.ctl->left.v, ~0ull);
-                        }
-                    }
-                    if (next != INT_MAX) {
-                        sched = true;
-                        lvl = next;
-                        st(&G->level, lvl);
-                        st(&G->gather_round, r + 1);
-                        st(&G->gmin[q], (int32_t)INT_MAX);
-                        atomicAdd(&G->levels, 1);
-                    }
-                }
-            }
-        }
-        const uint32_t n = sched ? (uint32_t)(e1 - e0) : 0u;
-        const uint32_t cnt = (n + kGatherChunk - 1) / kGatherChunk;
-        u64 base[3];
-        wave_alloc3(cnt, &M.ctl->ngth[q].v, 0u, nullptr, 0u, nullptr, base);
-        // Items {g, level, lo, hi} over the edge range, kGatherChunk edges each.
-        const uint32_t own = min(cnt, kOwnChunks);
-        for (uint32_t c = 0; c < own; ++c) {
-            const uint32_t a = (uint32_t)e0 + c * kGatherChunk;
-            st_item(&M.gth[q][base[0] + c],
-                    GatherItem{(int32_t)g, lvl, a, min(a + kGatherChunk, (uint32_t)e1)});
-        }
-        unsigned long long big = __ballot(cnt > own);
-        while (big) {
-            const int l = __ffsll(big) - 1;
-            big &= big - 1;
-            const uint32_t nc = __shfl(cnt, l, kWave);
-            const u64 b = __shfl(base[0], l, kWave);
-            const int32_t lg = __shfl((int32_t)g, l, kWave), ll = __shfl(lvl, l, kWave);
-            const uint32_t le0 = (uint32_t)__shfl(e0, l, kWave), le1 = (uint32_t)__shfl(e1, l, kWave);
-            for (uint32_t c = kOwnChunks + lane_id(); c < nc; c += kWave) {
-                const uint32_t a = le0 + c * kGatherChunk;
-                st_item(&M.gth[q][b + c], GatherItem{lg, ll, a, min(a + kGatherChunk, le1)});
-            }
-        }
-    }
-}
-
-__device__ __forceinline__ void multi_phase_a(const PeelArgs &P, const MultiArgs &M, int p,
-                                              u64 nf, u64 ngth, int64_t wid, int64_t nwaves,
-                                              u64 &upd) {
-    MultiCtl *C = M.ctl;
-    const int q = p ^ 1;
-    const int64_t total = (int64_t)(nf + ngth);
-    for (int64_t i = wid; i < total; i += nwaves) {
-        if (i >= (int64_t)nf) {
-            // Gather item: the graph's remaining edges at or below its level
-            // become the next frontier; the smallest support above it is kept
-            // for a jump.  Each lane reads kGatherPerLane edges at once.
-            const GatherItem it = ld_item(&M.gth[p][i - (int64_t)nf]);
-            int32_t ph[kGatherPerLane], sv[kGatherPerLane];
-#pragma unroll
-            for (int k = 0; k < kGatherPerLane; ++k) {
-                const uint32_t e = it.lo + k * kWave + lane_id();
-                ph[k] = 0;
-                sv[k] = INT_MAX;
-                if (e < it.hi) {
-                    ph[k] = ld(&P.phi[e]);
-                    sv[k] = ld(&P.sup[e]);
-                }
-            }
-            int32_t mn = INT_MAX;
-            uint32_t lo[kGatherPerLane], hi[kGatherPerLane];
-            bool take[kGatherPerLane];
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < kGatherPerLane; ++k) {
-                const uint32_t e = it.lo + k * kWave + lane_id();
-                const bool live = e < it.hi && ph[k] < 0;
-                take[k] = live && sv[k] <= it.level;
-                if (live && !take[k]) mn = min(mn, sv[k]);
-                lo[k] = hi[k] = 0;
-                if (take[k]) {
-                    lo[k] = (uint32_t)P.link_off[e];
-                    hi[k] = (uint32_t)P.link_off[(int64_t)e + 1];
-                }
-                any |= take[k];
-            }
-            uint32_t kk[kGatherPerLane], tot = 0;
-#pragma unroll
-            for (int k = 0; k < kGatherPerLane; ++k) {
-                kk[k] = take[k] ? link_chunks(lo[k], hi[k]) : 0u;
-                tot += kk[k];
-            }
-            u64 base[3];
-            wave_alloc3(tot, &C->nf[q].v, 0u, nullptr, 0u, nullptr, base);
-            u64 b = base[0];
-#pragma unroll
-            for (int k = 0; k < kGatherPerLane; ++k) {
-                put_front(P, q, b, (int32_t)(it.lo + k * kWave + lane_id()), lo[k], hi[k], kk[k],
-                          it.level);
-                b += kk[k];
-            }
-            mn = wave_min(mn);
-            if (__ballot(any) != 0 && lane_id() == 0) set_front_flag(M, it.g, q);
-            if (lane_id() == 0 && mn != INT_MAX) atomicMin(&M.gs[it.g].gmin[p], mn);
-            continue;
-        }
-        const FrontItem it = ld_item(&P.front[p][i]);
-        const int32_t level = it.level;
-        const uint32_t j = it.lo + lane_id();
-        const bool has = j < it.hi;
-        uint32_t bit = 0, old = 0, w0 = 0, w1 = 0, tlo = 0, thi = 0;
-        int32_t blm = 0, twin = 0, kb = 0, tg = 0;
-        if (has) {
-            const uint3 lk = P.link[j];
-            const uint32_t w = lk.x;
-            blm = (int32_t)lk.y;
-            twin = (int32_t)(lk.z & kEdgeMask);
-            bit = 1u << (w & 31);
-            w0 = P.bwoff[blm];
-            w1 = P.bwoff[blm + 1];
-            kb = ld(&P.bk[blm]);
-            tlo = (uint32_t)P.link_off[twin];
-            thi = (uint32_t)P.link_off[(int64_t)twin + 1];
-            tg = M.gid[twin];
-            old = atomicAnd(&P.alive[w >> 5], ~bit);
-        }
-        const bool won = has && (old & bit);
-        const int32_t d = max(kb - 1, 0);
-        const bool dec = won && d > 0;
-        int32_t oc = 1, otw = 0;
-        if (won) {
-            oc = atomicAdd(&P.bc[blm], 1);
-            otw = atomicSub(&P.sup[twin], d);
-        }
-        const bool first = oc == 0;
-        const uint32_t nch = first ? (w1 - w0 + kWedgeChunk - 1) / kWedgeChunk : 0u;
-        const bool tf = dec && otw > level && otw - d <= level;
-        const uint32_t tk = tf ? link_chunks(tlo, thi) : 0u;
-        u64 base[3];
-        wave_alloc3(nch, &C->ntc[p].v, tk, &C->nf[q].v, 0u, nullptr, base);
-        put_bloom_items(M.tc[p], base[0], nch, blm, level, w0, w1);
-        put_front(P, q, base[1], twin, tlo, thi, tk, level);
-        if (tf) set_front_flag(M, tg, q);
-        upd += dec ? 1 : 0;
-    }
-}
-
-__device__ __forceinline__ void multi_phase_b(const PeelArgs &P, const MultiArgs &M, int p,
-                                              u64 ntc, int64_t wid, int64_t nwaves, u64 &upd,
-                                              u64 &visits) {
-    MultiCtl *C = M.ctl;
-    const int q = p ^ 1;
-    for (int64_t i = wid; i < (int64_t)ntc; i += nwaves) {
-        const MBloomItem it = ld_item(&M.tc[p][i]);
-        const int32_t b = it.b;
-        const int32_t level = it.level;
-        const uint32_t nch = it.meta >> 7;
-        const uint32_t w = it.lo + lane_id();
-        const bool inr = w < it.lo + (it.meta & 127u);
-        uint32_t word = 0;
-        int32_t ea = 0, eb = 0;
-        if (inr) {
-            ea = P.wea[w];
-            eb = P.web[w];
-            word = ld(&P.alive[w >> 5]);
-        }
-        const int32_t c = ld(&P.bc[b]);
-        const int32_t kn = ld(&P.bk[b]) - c;
-        const bool live = inr && kn > 0 && ((word >> (w & 31)) & 1u);
-        int32_t o1 = 0, o2 = 0;
-        if (live) {
-            o1 = atomicSub(&P.sup[ea], c);
-            o2 = atomicSub(&P.sup[eb], c);
-        }
-        bool last = false;
-        if (lane_id() == 0 && kn != INT_MIN)
-            last = nch == 1 || atomicAdd(&P.bdone[b], 1) == (int32_t)nch - 1;
-        const bool f1 = live && o1 > level && o1 - c <= level;
-        const bool f2 = live && o2 > level && o2 - c <= level;
-        uint32_t lo1 = 0, hi1 = 0, lo2 = 0, hi2 = 0;
-        int32_t g1 = 0, g2 = 0;
-        if (f1) {
-            lo1 = (uint32_t)P.link_off[ea];
-            hi1 = (uint32_t)P.link_off[(int64_t)ea + 1];
-            g1 = M.gid[ea];
-        }
-        if (f2) {
-            lo2 = (uint32_t)P.link_off[eb];
-            hi2 = (uint32_t)P.link_off[(int64_t)eb + 1];
-            g2 = M.gid[eb];
-        }
-        const uint32_t k1 = f1 ? link_chunks(lo1, hi1) : 0u;
-        const uint32_t k2 = f2 ? link_chunks(lo2, hi2) : 0u;
-        u64 base[3];
-        wave_alloc3(k1 + k2, &C->nf[q].v, 0u, nullptr, 0u, nullptr, base);
-        put_front(P, q, base[0], ea, lo1, hi1, k1, level);
-        put_front(P, q, base[0] + k1, eb, lo2, hi2, k2, level);
-        if (f1) set_front_flag(M, g1, q);
-        if (f2) set_front_flag(M, g2, q);
-        upd += live ? 2 : 0;
-        if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
-        if (last) {
-            st(&P.bk[b], kn);
-            st(&P.bc[b], 0);
-            st(&P.bdone[b], 0);
-            visits += 1;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M, GridBar *B,
-                                                        int64_t max_rounds, int prof) {
-    MultiCtl *C = M.ctl;
-    __shared__ u64 s_nf, s_ngth, s_ntc, s_left;
-    __shared__ int s_ok;
-    u64 gen_local = 0;
-    const int64_t wid = (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
-    const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
-    const int64_t tid = wid * kWave + lane_id();
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    u64 upd = 0, visits = 0;
-    if (threadIdx.x == 0) {
-        s_left = ld(&C->left.v);
-        s_nf = ld(&C->nf[0].v);
-        s_ngth = ld(&C->ngth[0].v);
-        s_ok = 1;
-    }
-    __syncthreads();
-    int64_t r = 0;
-    for (; r < max_rounds && s_left > 0 && s_ok; ++r) {
-        const int p = (int)(r & 1), q = p ^ 1;
-        const u64 nf = s_nf, ngth = s_ngth;
-        u64 t0 = 0, t1 = 0, t2 = 0, t3 = 0, t4 = 0;
-        if (prof && lead) t0 = wall_clock64();
-        if (lead) st(&C->ntc[q].v, (u64)0);
-        multi_decide(M, r, p, tid, nwaves * kWave);
-        if (prof && lead) t1 = wall_clock64();
-        multi_phase_a(P, M, p, nf, ngth, wid, nwaves, upd);
-        if (prof && lead) t2 = wall_clock64();
-        drain_memory();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_ok = grid_arrive_wait(B, gen_local);
-            s_ntc = ld(&C->ntc[p].v);
-        }
-        __syncthreads();
-        if (!s_ok) break;
-        if (prof && lead) t3 = wall_clock64();
-        if (lead) {
-            st(&C->nf[p].v, (u64)0);
-            st(&C->ngth[p].v, (u64)0);
-        }
-        multi_phase_b(P, M, p, s_ntc, wid, nwaves, upd, visits);
-        drain_memory();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_ok = grid_arrive_wait(B, gen_local);
-            s_left = ld(&C->left.v);
-            s_nf = ld(&C->nf[q].v);
-            s_ngth = ld(&C->ngth[q].v);
-        }
-        __syncthreads();
-        if (prof && lead) {
-            t4 = wall_clock64();
-            C->prof[0] += t1 - t0;
-            C->prof[1] += t2 - t1;
-            C->prof[2] += t3 - t2;
-            C->prof[4] += t4 - t3;
-        }
-    }
-    upd = wave_sum(upd);
-    visits = wave_sum(visits);
-    if (lane_id() == 0) {
-        if (upd) atomicAdd(&C->updates.v, upd);
-        if (visits) atomicAdd(&C->bloom_visits.v, visits);
-    }
-    if (lead) st(&C->rounds, (u64)r);
-}
-
 // ---------------------------------------------------------------- refill
 
 __global__ __launch_bounds__(kBlock) void k_refill_compact(const int32_t *list, int64_t n,
@@ -1423,37 +761,6 @@ __global__ __launch_bounds__(kBlock) void k_refill_gather(const int32_t *list, i
         const u64 slot = wave_alloc(take ? 1u : 0u, na);
         if (take) act[slot] = e;
     }
-}
-
-// Edges whose bitruss number is already fixed (progressive mode) start
-// removed-looking (phi >= 0) with an unreachable support, so no gather,
-// refill or crossing ever takes them.
-__global__ void k_init_peel(const uint64_t *supl, int64_t m, const int32_t *fixed, int32_t *sup,
-                            int32_t *phi, int64_t *sup_out) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t s = (int32_t)(supl[e] & 0xffffffffu);
-        const bool fx = fixed && fixed[e];
-        sup[e] = fx ? INT_MAX : s;
-        phi[e] = fx ? INT_MAX : -1;
-        if (sup_out) sup_out[e] = s;
-    }
-}
-
-__global__ void k_init_alive(const uint64_t *cursor, uint32_t *alive) {
-    const int64_t nw = (int64_t)(*cursor & 0xffffffffu);
-    const int64_t words = (nw + 31) / 32;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t rem = nw - i * 32;
-        alive[i] = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
-    }
-}
-
-__global__ void k_phi_out(const int32_t *phi, int64_t *out, int64_t m) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x)
-        out[e] = phi[e];
 }
 
 // ----------------------------------------------------------- host side
@@ -1714,150 +1021,6 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     }
     k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);
     BT_CHECK_LAUNCH();
-}
-
-namespace {
-
-__global__ void k_max_phi(const int32_t *phi, int64_t m, unsigned long long *out) {
-    unsigned long long v = 0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x)
-        v = max(v, (unsigned long long)max(phi[e], 0));
-    for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, (unsigned long long)__shfl_xor(v, d, kWave));
-    if (lane_id() == 0) atomicMax(out, v);
-}
-
-__global__ void k_multi_init(const int64_t *off, int32_t ng, int32_t *gid) {
-    for (int32_t g = blockIdx.x; g < ng; g += gridDim.x)
-        for (int64_t e = off[g] + threadIdx.x; e < off[g + 1]; e += blockDim.x) gid[e] = g;
-}
-
-}  // namespace
-
-void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
-                const std::vector<int64_t> &off, PeelCounters &pc, Workspace &ws, hipStream_t s) {
-    const int64_t m = r.m;
-    const int32_t ng = (int32_t)off.size() - 1;
-    if (m == 0) return;
-    if (2 * ix.n_w >= (int64_t)UINT32_MAX)
-        throw Error{BT_EOVERFLOW, "edge-to-wedge links must be below 2^32"};
-    const int64_t nb = ix.n_b > 0 ? ix.n_b : 1;
-    const int64_t words = (ix.n_w + 31) / 32 + 1;
-    const int64_t max_tc = nb + ix.n_w / kWedgeChunk + 1;
-    const int64_t max_front = m + 2 * ix.n_w / kLinkChunk + 1;
-    const int64_t max_gth = m / kGatherChunk + ng + 1;
-    PeelArgs P{};
-    P.sup = ws.get<int32_t>("peel_sup", m);
-    P.phi = ws.get<int32_t>("peel_phi", m);
-    P.alive = ws.get<uint32_t>("peel_alive", words);
-    P.bc = ws.get<int32_t>("peel_bc", nb);
-    P.bdone = ws.get<int32_t>("peel_bdone", nb);
-    P.bk = ix.bk;
-    P.bwoff = ix.bwoff;
-    P.wea = ix.wea;
-    P.web = ix.web;
-    P.wbl = ix.wbl;
-    P.link_off = ix.link_off;
-    P.link = ix.link;
-    P.front[0] = ws.get<FrontItem>("peel_front0", max_front);
-    P.front[1] = ws.get<FrontItem>("peel_front1", max_front);
-    P.prof = 0;
-    MultiArgs M{};
-    M.ctl = ws.get<MultiCtl>("pm_ctl", 1);
-    M.gs = ws.get<GState>("pm_gs", ng);
-    int32_t *gid = ws.get<int32_t>("pm_gid", m);
-    M.gid = gid;
-    M.ng = ng;
-    M.front[0] = P.front[0];
-    M.front[1] = P.front[1];
-    M.tc[0] = ws.get<MBloomItem>("pm_tc0", max_tc);
-    M.tc[1] = ws.get<MBloomItem>("pm_tc1", max_tc);
-    M.gth[0] = ws.get<GatherItem>("pm_gth0", max_gth);
-    M.gth[1] = ws.get<GatherItem>("pm_gth1", max_gth);
-    int64_t *doff = ws.get<int64_t>("pm_off", ng + 1);
-
-    k_init_peel<<<grid_for(m, 256, 16384), 256, 0, s>>>(ix.supl, m, nullptr, P.sup, P.phi, sup_out);
-    BT_CHECK_LAUNCH();
-    k_init_alive<<<grid_for(words, 256, 16384), 256, 0, s>>>(ix.cursor, P.alive);
-    BT_CHECK_LAUNCH();
-    BT_HIP(hipMemsetAsync(P.bc, 0, sizeof(int32_t) * nb, s));
-    BT_HIP(hipMemsetAsync(P.bdone, 0, sizeof(int32_t) * nb, s));
-    BT_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (ng + 1), hipMemcpyHostToDevice, s));
-    k_multi_init<<<std::min(ng, 4096), 256, 0, s>>>(doff, ng, gid);
-    BT_CHECK_LAUNCH();
-    // Every graph starts as if round -1 had been a gather that took nothing
-    // and saw minimum support 0: round 0 schedules its gather at level 0.
-    std::vector<GState> gs(ng);
-    int64_t left = 0;
-    for (int32_t g = 0; g < ng; ++g) {
-        GState &G = gs[g];
-        std::memset(&G, 0, sizeof G);
-        const int64_t mg = off[g + 1] - off[g];
-        G.state = mg > 0 ? kGsNormal : kGsDone;
-        G.level = -1;
-        G.gmin[0] = INT_MAX;
-        G.gmin[1] = 0;
-        G.e0 = (int32_t)off[g];
-        G.e1 = (int32_t)off[g + 1];
-        G.gather_round = -1;
-        left += mg > 0 ? 1 : 0;
-    }
-    BT_HIP(hipMemcpyAsync(M.gs, gs.data(), sizeof(GState) * ng, hipMemcpyHostToDevice, s));
-    MultiCtl mc{};
-    mc.left.v = (u64)left;
-    BT_HIP(hipMemcpyAsync(M.ctl, &mc, sizeof mc, hipMemcpyHostToDevice, s));
-    GridBar *bar = ws.get<GridBar>("peel_bar", 1);
-    BT_HIP(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
-    int dev = 0, cus = 0, occ = 0;
-    BT_HIP(hipGetDevice(&dev));
-    BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    BT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_peel_multi, kPBlock, 0));
-    const int pblocks = peel_grid(r.tp, cus, occ * cus);
-    int64_t max_rounds = 8 * m + 64;
-    int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
-    std::lock_guard<std::mutex> coop_lock(coop_mutex());
-    hipEvent_t ev0, ev1;
-    BT_HIP(hipEventCreate(&ev0));
-    BT_HIP(hipEventCreate(&ev1));
-    BT_HIP(hipEventRecord(ev0, s));
-    void *args[] = {&P, &M, &bar, &max_rounds, &prof};
-    BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_multi, dim3(pblocks), dim3(kPBlock),
-                                      args, 0, s));
-    BT_HIP(hipEventRecord(ev1, s));
-    MultiCtl hc{};
-    int32_t fail = 0;
-    BT_HIP(hipMemcpyAsync(&hc, M.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
-    BT_HIP(hipMemcpyAsync(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost, s));
-    BT_HIP(hipMemcpyAsync(gs.data(), M.gs, sizeof(GState) * ng, hipMemcpyDeviceToHost, s));
-    BT_HIP(hipStreamSynchronize(s));
-    float t = 0.f;
-    BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
-    if (hc.left.v != 0) throw Error{BT_EDEVICE, "batch peel stopped early"};
-    pc.kernel_ms += t;
-    pc.launches += 1;
-    pc.rounds = (int64_t)hc.rounds;
-    pc.updates = (int64_t)hc.updates.v;
-    pc.bloom_visits = (int64_t)hc.bloom_visits.v;
-    if (prof)
-        std::fprintf(stderr, "[multi] rounds %llu block0 us: decide %.0f phaseA %.0f bar1 %.0f phaseB+bar2 %.0f\n",
-                     hc.rounds, hc.prof[0] / 100.0, hc.prof[1] / 100.0, hc.prof[2] / 100.0,
-                     hc.prof[4] / 100.0);
-    for (const GState &G : gs) {
-        pc.levels = std::max<int64_t>(pc.levels, (int64_t)G.levels);
-    }
-    k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);
-    BT_CHECK_LAUNCH();
-    unsigned long long *mx = ws.get<unsigned long long>("pm_max", 1);
-    BT_HIP(hipMemsetAsync(mx, 0, sizeof *mx, s));
-    k_max_phi<<<grid_for(m, 256, 4096), 256, 0, s>>>(P.phi, m, mx);
-    BT_CHECK_LAUNCH();
-    unsigned long long hmx = 0;
-    BT_HIP(hipMemcpyAsync(&hmx, mx, sizeof hmx, hipMemcpyDeviceToHost, s));
-    BT_HIP(hipStreamSynchronize(s));
-    pc.max_phi = (int64_t)hmx;
 }
 
 }  // namespace bt
