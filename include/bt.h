@@ -36,8 +36,11 @@
  *   Errors: a non-zero bt_status leaves outputs unspecified;
  *     bt_last_error() returns a thread-local message for the last failure.
  *   Threading: calls that use the shared workspace (bt_support,
- *     bt_index_build, bt_decompose, bt_decompose_batch) serialise on an
- *     internal lock.
+ *     bt_index_build, bt_decompose, bt_decompose_variant, bt_decompose_pc,
+ *     bt_decompose_batch, bt_bitruss_components, bt_tune) serialise on an
+ *     internal lock; engines use workspaces of their own.  Cooperative peel
+ *     launches (all of the above that peel, and engine batches) run one at
+ *     a time in the process.
  */
 #ifndef BT_H
 #define BT_H
