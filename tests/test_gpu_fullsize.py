@@ -101,3 +101,26 @@ def test_request_graph_2m_digest():
         assert sha(phi_e.cpu().numpy()) == want["phi_sha256"]
     finally:
         eng.bt_engine_destroy()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_pool4096_batched_digests():
+    """The whole 4,096-graph pool as one batched call (as the benchmark times
+    it): the concatenated supports and bitruss numbers equal the oracle's."""
+    import concurrent.futures as cf
+    want = GOLD["pool:4096"]
+    assert want["generator_version"] == synth.GENERATOR_VERSION
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        gs = list(ex.map(synth.batch_graph, range(4096), chunksize=32))
+    dgs = [binding.DeviceGraph.upload(g) for g in gs]
+    sups, phis, st = binding.bt_decompose_batch(dgs, stats=True)
+    torch.cuda.synchronize()
+    hs, hp = hashlib.sha256(), hashlib.sha256()
+    for s, p in zip(sups, phis):
+        hs.update(np.ascontiguousarray(s.cpu().numpy(), dtype="<i8").tobytes())
+        hp.update(np.ascontiguousarray(p.cpu().numpy(), dtype="<i8").tobytes())
+    assert st["butterflies"] == want["butterflies"]
+    assert hs.hexdigest() == want["sup_sha256"]
+    assert hp.hexdigest() == want["phi_sha256"]
