@@ -168,7 +168,14 @@ typedef enum bt_peel_variant {
      * one, as when each removed edge updates its blooms on its own
      * (Algorithm 4's removal step).  The bloom's wedges are still read once
      * per round. */
-    BT_PEEL_BATCH_EDGE = 1
+    BT_PEEL_BATCH_EDGE = 1,
+    /* BiT-BU++, or BiT-PC (bt_decompose_pc, tau = 0.05) when the graph has at
+     * least 16,384 butterflies per edge: there the peel is bound by support
+     * updates, which BiT-PC cuts (20M-edge hub graph, 43k per edge: 40.6 s
+     * against 67.4 s), while below it the rounds bound it and BiT-PC's extra
+     * passes cost more (5M-edge Chung-Lu graph, 930 per edge; 2M-edge
+     * request graph, 5.9k per edge: equal).  Decided after the index build. */
+    BT_PEEL_AUTO = 2
 } bt_peel_variant;
 
 /*

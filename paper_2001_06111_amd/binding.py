@@ -211,7 +211,7 @@ def bt_tune_load(path: str):
     _check(load().bt_tune_load(os.fsencode(path)))
 
 
-BT_PEEL_BATCH_BLOOM, BT_PEEL_BATCH_EDGE = 0, 1
+BT_PEEL_BATCH_BLOOM, BT_PEEL_BATCH_EDGE, BT_PEEL_AUTO = 0, 1, 2
 
 
 def bt_decompose_variant(g: DeviceGraph, variant: int, want_sup: bool = True,

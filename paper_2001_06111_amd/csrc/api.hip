@@ -160,13 +160,24 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
 }  // namespace
 
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
-                    Workspace &ws, hipStream_t stream, bool unit_updates) {
+                    Workspace &ws, hipStream_t stream, bool unit_updates, bool auto_pc) {
     Events ev(stats != nullptr, stream);
     ev.mark(0);
     RankCSR r;
     IndexArrays ix;
     build_all(g, r, ix, false, nullptr, ws, stream, &ev);
     ev.mark(3);
+    if (auto_pc && g.m > 0) {
+        // Where support updates, not rounds, bound the peel (hub-heavy
+        // graphs), BiT-PC's smaller updates pay for its extra passes.
+        int64_t *hb = ws.host(2);
+        BT_HIP(hipMemcpyAsync(hb, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        BT_HIP(hipStreamSynchronize(stream));
+        if (hb[0] / g.m >= kAutoPcButterfliesPerEdge) {
+            decompose_pc_impl(g, kAutoPcTau, sup_out, phi_out, stats, ws, stream);
+            return;
+        }
+    }
     PeelCounters pc;
     PeelOptions o;
     o.unit_updates = unit_updates;
@@ -657,11 +668,12 @@ bt_status bt_decompose_variant(const bt_csr *g, int32_t variant, int64_t *sup_ou
     return guard([&] {
         check_graph(g);
         if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
-        if (variant != BT_PEEL_BATCH_BLOOM && variant != BT_PEEL_BATCH_EDGE)
+        if (variant != BT_PEEL_BATCH_BLOOM && variant != BT_PEEL_BATCH_EDGE &&
+            variant != BT_PEEL_AUTO)
             throw Error{BT_EINVAL, "unknown peel variant"};
         std::lock_guard<std::mutex> lk(lib().mu);
         decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream,
-                       variant == BT_PEEL_BATCH_EDGE);
+                       variant == BT_PEEL_BATCH_EDGE, variant == BT_PEEL_AUTO);
     });
 }
 

@@ -158,8 +158,13 @@ void mark_fixed(IndexArrays &ix, const int32_t *fixed, hipStream_t s);
 
 // Whole decompositions (api.hip): one graph, or many as disjoint unions.
 // `unit_updates`: the peel without batch bloom processing (ablation).
+// `auto_pc`: after the index build, switch to BiT-PC when the graph has at
+// least kAutoPcButterfliesPerEdge butterflies per edge.
 void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
-                    Workspace &ws, hipStream_t stream, bool unit_updates = false);
+                    Workspace &ws, hipStream_t stream, bool unit_updates = false,
+                    bool auto_pc = false);
+constexpr int64_t kAutoPcButterfliesPerEdge = 16384;
+constexpr double kAutoPcTau = 0.05;
 // Measures candidate launch parameters on these graphs (one graph, or a
 // batch) and stores the best for their kind and size class (tune.hip).
 TuneParams autotune(const bt_csr *gs, int32_t n, uint32_t what, Workspace &ws, hipStream_t s);

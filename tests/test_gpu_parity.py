@@ -123,6 +123,22 @@ def test_batch_edge_variant():
     assert ei.value.status == binding.BT_EINVAL
 
 
+def test_auto_variant():
+    """BT_PEEL_AUTO gives the same numbers on either side of its switch:
+    below 16,384 butterflies per edge through the plain peel, above it (a
+    complete bipartite graph, whose closed form is known) through BiT-PC."""
+    for g in [graphs.worked_example(True)[0], synth.scaled_chunglu(20_000, seed=3)]:
+        _, phi, _ = binding.bt_decompose_variant(upload(g), binding.BT_PEEL_AUTO)
+        assert np.array_equal(phi.cpu().numpy(), oracle_all(g)[2]), g.name
+    a, b = 300, 300
+    g = synth.complete(a, b)
+    assert (a - 1) * (b - 1) // 4 >= 16384  # butterflies per edge
+    sup, phi, st = binding.bt_decompose_variant(upload(g), binding.BT_PEEL_AUTO, stats=True)
+    want = (a - 1) * (b - 1)
+    assert st["butterflies"] == (a * (a - 1) // 2) * (b * (b - 1) // 2)
+    assert (sup.cpu().numpy() == want).all() and (phi.cpu().numpy() == want).all()
+
+
 def test_invalid_input_rejected():
     g = synth.uniform(10, 10, 30, 1)
     bad_col = g.col.copy()
