@@ -305,12 +305,12 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   sup_out may be NULL.  Results equal bt_decompose on the same graph.
  * A free slot admits, in arrival order, queued requests of the class of
  *   the oldest one that fit the budget left by the other slots, and
- *   decomposes them as one batch (bt_decompose_batch semantics): requests
- *   of at least 2^19 edges are batched only with each other, at most four
- *   at a time; smaller ones are batched only with each other.  A batch of
- *   small requests goes first while any is queued, unless the oldest large
- *   request has waited 10 s.  Requests that arrive meanwhile go to the next
- *   free slot, so batches overlap on the device.
+ *   decomposes them as one batch (bt_decompose_batch semantics).  A batch
+ *   holds one size class: below 2^14 edges, below 2^19, or larger (at most
+ *   four of those at a time).  The smallest class queued goes first, unless
+ *   the oldest request of a larger class has waited 10 s.  Requests that
+ *   arrive meanwhile go to the next free slot, so batches overlap on the
+ *   device.
  * bt_engine_poll: moves up to `cap` completed (id, status) pairs to the
  *   caller's host arrays; *n_done receives how many.
  * bt_engine_drain: blocks until every submitted request has completed.

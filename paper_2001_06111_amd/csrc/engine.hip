@@ -2,16 +2,17 @@
 //
 // Requests (device CSRs with caller-owned outputs) are queued with a
 // device-memory estimate taken at submit time.  Each worker slot owns a HIP
-// stream and a workspace; when a slot is free it admits, in arrival order,
-// queued requests of the class of the oldest one while their estimates fit
-// the engine's memory budget (less what the other slots hold), and
-// decomposes them together as one disjoint union.  Large requests (at
-// least kLargeEdges edges) are batched only with large ones, a few at a
-// time, small requests only with small ones, so a small request never waits
-// for a large graph's peel inside its batch.  Small batches go first unless
-// the oldest large request has waited kLargeWaitS.  Requests that arrive while batches run are admitted by the next
-// free slot, so batches on different slots overlap on the GPU.  Each result
-// equals the plain single-graph decomposition of the request.
+// stream and a workspace; when a slot is free it picks a size class
+// (below 2^14 edges, below 2^19, larger) and admits, in arrival order,
+// queued requests of that class while their estimates fit the engine's
+// memory budget (less what the other slots hold), and decomposes them
+// together as one disjoint union; large requests a few at a time.  A batch
+// never mixes classes, so a small request never waits inside its batch for
+// a larger graph's peel.  The smallest class present goes first unless the
+// oldest request of a larger class has waited kLargeWaitS.  Requests that
+// arrive while batches run are admitted by the next free slot, so batches on
+// different slots overlap on the GPU.  Each result equals the plain
+// single-graph decomposition of the request.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -39,14 +40,21 @@ struct Done {
     bt_status st;
 };
 
+// Size classes: a batch holds requests of one class.  A batch runs as many
+// peel rounds as its slowest graph needs, so small graphs are not held up
+// by medium ones in their own batch.
 constexpr int64_t kLargeEdges = int64_t(1) << 19;
+constexpr int64_t kMediumEdges = int64_t(1) << 14;
+constexpr int kClasses = 3;
+inline int size_class_of(int64_t m) { return m >= kLargeEdges ? 2 : m >= kMediumEdges ? 1 : 0; }
 // Large requests share a batch too (one union, one shared level, so their
 // rounds overlap: four 2M-edge graphs take 1.7x less time together than one
 // after another), but at most this many, to bound each one's latency.
 constexpr int32_t kLargePerBatch = 4;
-// Small batches go first (they take a fraction of a large batch's time),
-// unless the oldest large request has waited this long (so a steady stream
-// of small requests cannot starve large ones).
+// Batches of the smallest class present go first (they take a fraction of
+// a larger class's time), unless the oldest request of a larger class has
+// waited this long (so a steady stream of small requests cannot starve
+// larger ones).
 constexpr double kLargeWaitS = 10.0;
 
 }  // namespace
@@ -73,24 +81,28 @@ struct bt_engine {
     int64_t batches = 0, admitted = 0;
 
     void worker_loop(int slot);
-    bool pick_large() const;
-    const Request *first_of(bool large) const;
+    int pick_class() const;
+    const Request *first_of(int cls) const;
 };
 
-const Request *bt_engine::first_of(bool large) const {
+const Request *bt_engine::first_of(int cls) const {
     for (const Request &r : queue)
-        if ((r.g.m >= kLargeEdges) == large) return &r;
+        if (size_class_of(r.g.m) == cls) return &r;
     return nullptr;
 }
 
-// The class of the next batch (call with mu held).
-bool bt_engine::pick_large() const {
-    const Request *l = first_of(true);
-    if (!l) return false;
-    if (!first_of(false)) return true;
-    const double waited =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - l->t).count();
-    return waited >= kLargeWaitS;
+// The class of the next batch (call with mu held and the queue non-empty):
+// the largest class whose oldest request has waited kLargeWaitS, else the
+// smallest class present.
+int bt_engine::pick_class() const {
+    const auto now = std::chrono::steady_clock::now();
+    for (int c = kClasses - 1; c > 0; --c) {
+        const Request *r = first_of(c);
+        if (r && std::chrono::duration<double>(now - r->t).count() >= kLargeWaitS) return c;
+    }
+    for (int c = 0; c < kClasses; ++c)
+        if (first_of(c)) return c;
+    return 0;
 }
 
 void bt_engine::worker_loop(int slot) {
@@ -104,19 +116,19 @@ void bt_engine::worker_loop(int slot) {
         int64_t bytes = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
-            bool large = false;
+            int cls = 0;
             cv_work.wait(lk, [&] {
                 if (stop) return true;
                 if (queue.empty()) return false;
-                large = pick_large();
-                return reserved + first_of(large)->bytes <= budget;
+                cls = pick_class();
+                return reserved + first_of(cls)->bytes <= budget;
             });
             if (stop) break;  // destroy drains the queue before it stops workers
             // Admit requests of the chosen class in arrival order while the
             // budget allows.
-            const int32_t cap = large ? std::min(max_batch, kLargePerBatch) : max_batch;
+            const int32_t cap = cls == 2 ? std::min(max_batch, kLargePerBatch) : max_batch;
             for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < cap;) {
-                if ((it->g.m >= kLargeEdges) != large) {
+                if (size_class_of(it->g.m) != cls) {
                     ++it;
                     continue;
                 }
