@@ -124,3 +124,17 @@ def test_pool4096_batched_digests():
     assert st["butterflies"] == want["butterflies"]
     assert hs.hexdigest() == want["sup_sha256"]
     assert hp.hexdigest() == want["phi_sha256"]
+
+
+def test_pc_fullsize_digests(c1):
+    """BiT-PC (the progressive compression of Section V-C) at full size: on
+    the 5M-edge graph and on the 2M-edge request graph its bitruss numbers
+    equal the oracle's, bit for bit."""
+    g, _, _, _ = c1
+    _, phi, st = binding.bt_decompose_pc(binding.DeviceGraph.upload(g), tau=0.05, stats=True,
+                                         want_sup=False)
+    assert sha(phi.cpu().numpy()) == GOLD[g.name]["phi_sha256"]
+    assert st["passes"] > 1
+    b = synth.big_serving_graph(0)
+    _, phi, _ = binding.bt_decompose_pc(binding.DeviceGraph.upload(b), tau=0.1, want_sup=False)
+    assert sha(phi.cpu().numpy()) == GOLD["big:1"]["phi_sha256"]
