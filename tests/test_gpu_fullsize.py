@@ -138,3 +138,18 @@ def test_pc_fullsize_digests(c1):
     b = synth.big_serving_graph(0)
     _, phi, _ = binding.bt_decompose_pc(binding.DeviceGraph.upload(b), tau=0.1, want_sup=False)
     assert sha(phi.cpu().numpy()) == GOLD["big:1"]["phi_sha256"]
+
+
+@pytest.mark.slow
+def test_components_fullsize(c1):
+    """Connected components of two top k-bitrusses of the 5M-edge graph (the
+    bitruss numbers are the oracle's, by the digest test) against the
+    oracle's breadth-first search."""
+    from oracle import query
+    g, _, phi, _ = c1
+    dg = binding.DeviceGraph.upload(g)
+    dphi = torch.from_numpy(phi).cuda()
+    for k in (int(np.percentile(phi, 99.9)), int(phi.max())):
+        comp, n = binding.bt_bitruss_components(dg, dphi, k)
+        want, wn = query.bitruss_components(g.n_upper, g.n_lower, g.row_ptr, g.col, phi, k)
+        assert n == wn and np.array_equal(comp.cpu().numpy(), want), k
