@@ -139,6 +139,25 @@ def test_auto_variant():
     assert (sup.cpu().numpy() == want).all() and (phi.cpu().numpy() == want).all()
 
 
+def test_wedge_limit():
+    """K_{2500,2500}: 6.25M edges, about 5.2e9 priority-obeyed wedges, beyond
+    the index's 2^32 limit.  Support counting needs no index and returns the
+    closed form; a decomposition is refused with BT_EOVERFLOW before it
+    allocates the index, and the library works afterwards."""
+    a = b = 2500
+    row_ptr = (np.arange(a + 1, dtype=np.int64) * b)
+    col = np.tile(np.arange(b, dtype=np.int32), a)
+    dg = binding.DeviceGraph(a, b, torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda())
+    sup, bf = binding.bt_support(dg)
+    assert bf == (a * (a - 1) // 2) * (b * (b - 1) // 2)
+    assert bool((sup == (a - 1) * (b - 1)).all())
+    with pytest.raises(binding.BtError) as ei:
+        binding.bt_decompose(dg)
+    assert ei.value.status == binding.BT_EOVERFLOW
+    del dg, sup
+    _parity(synth.complete(7, 9))
+
+
 def test_invalid_input_rejected():
     g = synth.uniform(10, 10, 30, 1)
     bad_col = g.col.copy()
