@@ -438,6 +438,8 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
     flush_stats(C, upd, visits, unb);
 }
 
+// --- persistent cooperative kernel: rounds separated by grid barriers ---
+
 // Rebuild of the active set inside the persistent kernel, when it has run
 // dry: the remaining edges (phi < 0) are compacted from one list into the
 // other while their minimum support mn is found; a log2 histogram of

@@ -230,7 +230,7 @@ __device__ __forceinline__ void count_push(const PeelArgs &P, int q, int src, ui
         atomicAdd(src == kSrcTwin ? &P.ctl->push_twin[q].v : &P.ctl->push_surv[q].v, t);
 }
 
-// --- persistent cooperative kernel: rounds separated by grid barriers ---
+// --- cooperative kernels: workgroup size and the grid barrier ------------
 
 constexpr int kPBlock = 1024;  // 16 waves per CU (up to 128 VGPRs: four waves per SIMD)
 
