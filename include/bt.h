@@ -280,9 +280,14 @@ bt_status bt_bitruss_components(const bt_csr *g, const int64_t *phi, int64_t k,
 /*
  * Decompose many independent graphs in shared launches.  gs is a HOST
  * array of n_graphs descriptors (device CSRs); sup_out / phi_out are HOST
- * arrays of n_graphs device pointers (sup_out may be NULL, or hold NULLs).
- * Results equal bt_decompose on each graph.  stats (nullable) receives the
- * sums over all graphs (levels and rounds: the maximum).
+ * arrays of n_graphs device pointers (sup_out may be NULL, or hold NULLs;
+ * phi_out[i] may be NULL only for a graph without edges).  The graphs are
+ * decomposed as disjoint unions of at most 2^26 edges (larger ones alone),
+ * cut from the graphs in decreasing edge count; within a union every graph
+ * peels at its own level.  Results equal bt_decompose on each graph.
+ * stats (nullable) receives the sums over all graphs; rounds and
+ * peel_launches are summed over the unions, levels is the sum over the
+ * unions of each union's largest per-graph level count.
  */
 bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const *sup_out,
                              int64_t *const *phi_out, bt_stats *stats, hipStream_t stream);
