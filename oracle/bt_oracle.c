@@ -202,6 +202,93 @@ int64_t bto_edge_support(int32_t n_upper, const int64_t *row_ptr, const int32_t 
 }
 
 /*
+ * Rows of the remaining graph.  Each vertex keeps the edges it still has at
+ * the front of its row, in no particular order: nbr[p] is the other
+ * endpoint and eid[p] the edge at place p, len[x] the number of remaining
+ * edges of x, and pos[e] the place of edge e in its row.  Removing an edge
+ * moves the last remaining entry of the row into its place, so walks over
+ * the remaining graph never visit removed edges.
+ */
+typedef struct {
+    const int64_t *ptr;
+    int32_t *len;
+    int32_t *nbr;
+    int64_t *eid;
+    int64_t *pos;
+} rows_t;
+
+static int rows_init(rows_t *r, const side_t *s, int64_t m) {
+    r->ptr = s->ptr;
+    r->len = (int32_t *)malloc(((size_t)s->n + 1) * sizeof(int32_t));
+    r->nbr = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    r->eid = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    r->pos = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    if (!r->len || !r->nbr || !r->eid || !r->pos) return -1;
+    for (int32_t a = 0; a < s->n; ++a) {
+        r->len[a] = (int32_t)(s->ptr[a + 1] - s->ptr[a]);
+        for (int64_t p = s->ptr[a]; p < s->ptr[a + 1]; ++p) {
+            int64_t e = side_eid(s, p);
+            r->nbr[p] = s->adj[p];
+            r->eid[p] = e;
+            r->pos[e] = p;
+        }
+    }
+    return 0;
+}
+
+static void rows_remove(rows_t *r, int32_t a, int64_t e) {
+    int64_t p = r->pos[e];
+    int64_t last = r->ptr[a] + r->len[a] - 1;
+    r->nbr[p] = r->nbr[last];
+    r->eid[p] = r->eid[last];
+    r->pos[r->eid[p]] = p;
+    r->len[a]--;
+}
+
+static void rows_free(rows_t *r) {
+    free(r->len); free(r->nbr); free(r->eid); free(r->pos);
+}
+
+/* A frontier edge with the vertex whose row its enumeration marks. */
+typedef struct {
+    int32_t side;  /* 0: marks the upper endpoint's row, 1: the lower one's */
+    int32_t vtx;
+    int64_t e;
+} fkey_t;
+
+static int fkey_cmp(const void *pa, const void *pb) {
+    const fkey_t *a = (const fkey_t *)pa, *b = (const fkey_t *)pb;
+    if (a->side != b->side) return a->side < b->side ? -1 : 1;
+    if (a->vtx != b->vtx) return a->vtx < b->vtx ? -1 : 1;
+    return a->e < b->e ? -1 : (a->e > b->e);
+}
+
+enum { kGroup = 64 };
+
+/*
+ * The butterfly made of the frontier edge e and the edges f[0..2] of the
+ * remaining graph.  Only the frontier edge of smallest id in it destroys it
+ * (so it is destroyed once), lowering the support of each of its edges
+ * outside the frontier by one; an edge whose support thereby falls from
+ * above the level to the level joins the next frontier.  Returns 1 if e
+ * destroyed it.
+ */
+static inline int destroy(int64_t e, const int64_t f[3], const uint8_t *in_f, int64_t *s,
+                          int64_t level, int64_t *next, int64_t *n_next) {
+    for (int j = 0; j < 3; ++j)
+        if (in_f[f[j]] && f[j] < e) return 0;
+    for (int j = 0; j < 3; ++j) {
+        if (in_f[f[j]]) continue;
+        int64_t old = __atomic_fetch_sub(&s[f[j]], 1, __ATOMIC_RELAXED);
+        if (old > level && old - 1 <= level) {
+            int64_t slot = __atomic_fetch_add(n_next, 1, __ATOMIC_RELAXED);
+            next[slot] = f[j];
+        }
+    }
+    return 1;
+}
+
+/*
  * Bitruss numbers by level-synchronous bottom-up peeling with explicit
  * butterfly enumeration.
  *
@@ -234,6 +321,7 @@ int bto_bitruss(int32_t n_upper, int32_t n_lower, int64_t m,
     if (nthreads > 0) omp_set_num_threads(nthreads);
     if (graph_init(&g, n_upper, n_lower, m, row_ptr, col)) return -1;
     side_t U = upper_side(&g), Ls = lower_side(&g);
+    rows_t RU, RL;
     int64_t *s = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
     uint8_t *alive = (uint8_t *)malloc((size_t)(m > 0 ? m : 1));
     uint8_t *in_f = (uint8_t *)calloc((size_t)(m > 0 ? m : 1), 1);
@@ -243,7 +331,11 @@ int bto_bitruss(int32_t n_upper, int32_t n_lower, int64_t m,
     int32_t *urow = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
     int64_t *hop_u = (int64_t *)calloc((size_t)n_upper + 1, sizeof(int64_t));
     int64_t *hop_l = (int64_t *)calloc((size_t)n_lower + 1, sizeof(int64_t));
-    if (!s || !alive || !in_f || !front || !next || !rest || !urow || !hop_u || !hop_l) {
+    fkey_t *fkey = (fkey_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(fkey_t));
+    int64_t *gstart = (int64_t *)malloc((size_t)(m + 1) * sizeof(int64_t));
+    if (!s || !alive || !in_f || !front || !next || !rest || !urow || !hop_u || !hop_l ||
+        !fkey || !gstart ||
+        rows_init(&RU, &U, m) || rows_init(&RL, &Ls, m)) {
         graph_free(&g);
         return -1;
     }
@@ -256,15 +348,17 @@ int bto_bitruss(int32_t n_upper, int32_t n_lower, int64_t m,
     for (int32_t u = 0; u < n_upper; ++u)
         for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) urow[e] = u;
     /* hop(x) = sum of the degrees of x's neighbours: the number of entries
-     * an enumeration from x's side walks.  Used only to pick the cheaper
-     * of the two symmetric enumerations. */
+     * an enumeration from x's side walks in the whole graph.  Used only to
+     * pick the cheaper of the two symmetric enumerations. */
     for (int64_t e = 0; e < m; ++e) {
         int32_t u = urow[e], v = col[e];
         hop_u[u] += Ls.ptr[v + 1] - Ls.ptr[v];
         hop_l[v] += U.ptr[u + 1] - U.ptr[u];
     }
     for (int64_t e = 0; e < m; ++e) { alive[e] = 1; rest[e] = e; }
-    int64_t n_rest = m, n_front = 0, level = 0;
+    /* rest lists every remaining edge and possibly removed ones; it is
+     * compacted whenever more than half of its entries are removed. */
+    int64_t n_rest = m, n_alive = m, n_front = 0, level = 0;
     int64_t levels = 0, rounds = 0, destroyed = 0, max_phi = 0;
 
     int nthr = omp_get_max_threads();
@@ -281,22 +375,30 @@ int bto_bitruss(int32_t n_upper, int32_t n_lower, int64_t m,
         for (int32_t i = 0; i <= n_lower; ++i) mark_l[t][i] = -1;
     }
 
-    while (n_rest > 0) {
+    while (n_alive > 0) {
         if (n_front == 0) {
-            /* New level: drop removed edges from the remaining list, take
-             * the minimum remaining support and its edges. */
-            int64_t k = 0, mn = INT64_MAX;
+            /* New level: the minimum remaining support, then its edges. */
+            if (n_rest > 2 * n_alive) {
+                int64_t k = 0;
+                for (int64_t i = 0; i < n_rest; ++i)
+                    if (alive[rest[i]]) rest[k++] = rest[i];
+                n_rest = k;
+            }
+            int64_t mn = INT64_MAX;
+#pragma omp parallel for reduction(min : mn) schedule(static)
             for (int64_t i = 0; i < n_rest; ++i) {
                 int64_t e = rest[i];
-                if (!alive[e]) continue;
-                rest[k++] = e;
-                if (s[e] < mn) mn = s[e];
+                if (alive[e] && s[e] < mn) mn = s[e];
             }
-            n_rest = k;
-            if (n_rest == 0) break;
             if (mn > level) level = mn;
-            for (int64_t i = 0; i < n_rest; ++i)
-                if (s[rest[i]] <= level) front[n_front++] = rest[i];
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < n_rest; ++i) {
+                int64_t e = rest[i];
+                if (alive[e] && s[e] <= level) {
+                    int64_t slot = __atomic_fetch_add(&n_front, 1, __ATOMIC_RELAXED);
+                    front[slot] = e;
+                }
+            }
             ++levels;
         }
         ++rounds;
@@ -305,82 +407,93 @@ int bto_bitruss(int32_t n_upper, int32_t n_lower, int64_t m,
             phi_out[front[i]] = level;
         }
         if (level > max_phi) max_phi = level;
+        /* Each F-edge (u,v) enumerates from the side whose walk is shorter:
+         * side 0 marks N(u) and walks N(v) then N(w), side 1 the mirror.
+         * F-edges that mark the same vertex are taken in groups of at most
+         * kGroup, so a row is marked once per group. */
+        for (int64_t i = 0; i < n_front; ++i) {
+            int64_t e = front[i];
+            int32_t u = urow[e], v = col[e];
+            fkey[i].side = hop_l[v] <= hop_u[u] ? 0 : 1;
+            fkey[i].vtx = fkey[i].side == 0 ? u : v;
+            fkey[i].e = e;
+        }
+        qsort(fkey, (size_t)n_front, sizeof(fkey_t), fkey_cmp);
+        int64_t n_groups = 0;
+        for (int64_t i = 0; i < n_front; ++i)
+            if (i == 0 || fkey[i].side != fkey[i - 1].side || fkey[i].vtx != fkey[i - 1].vtx ||
+                i - gstart[n_groups - 1] == kGroup)
+                gstart[n_groups++] = i;
+        gstart[n_groups] = n_front;
         int64_t n_next = 0;
 #pragma omp parallel reduction(+ : destroyed)
         {
             int t = omp_get_thread_num();
             int32_t *mu = mark_u[t], *ml = mark_l[t];
             int64_t *eu = meid_u[t], *el = meid_l[t];
-#pragma omp for schedule(dynamic, 4)
-            for (int64_t i = 0; i < n_front; ++i) {
-                int64_t e = front[i];
-                int32_t u = urow[e], v = col[e];
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t gi = 0; gi < n_groups; ++gi) {
+                const int32_t stamp = (int32_t)gi;
+                const int32_t a = fkey[gstart[gi]].vtx;
                 int64_t f[3];
-                if (hop_l[v] <= hop_u[u]) {
-                    /* Mark the other remaining neighbours x of u, then walk
-                     * w in N(v) and x in N(w): (w,x) closes [u,v,w,x]. */
-                    for (int64_t p = U.ptr[u]; p < U.ptr[u + 1]; ++p)
-                        if (p != e && alive[p]) { ml[U.adj[p]] = (int32_t)i; el[U.adj[p]] = p; }
-                    for (int64_t q = Ls.ptr[v]; q < Ls.ptr[v + 1]; ++q) {
-                        int32_t w = Ls.adj[q];
-                        int64_t ewv = Ls.eid[q];
-                        if (w == u || !alive[ewv]) continue;
-                        for (int64_t r = U.ptr[w]; r < U.ptr[w + 1]; ++r) {
-                            int32_t x = U.adj[r];
-                            if (x == v || !alive[r] || ml[x] != (int32_t)i) continue;
-                            f[0] = ewv; f[1] = el[x]; f[2] = r;
-                            int owner = 1;
-                            for (int j = 0; j < 3; ++j)
-                                if (in_f[f[j]] && f[j] < e) owner = 0;
-                            if (!owner) continue;
-                            ++destroyed;
-                            for (int j = 0; j < 3; ++j) {
-                                if (in_f[f[j]]) continue;
-                                int64_t old = __atomic_fetch_sub(&s[f[j]], 1, __ATOMIC_RELAXED);
-                                if (old > level && old - 1 <= level) {
-                                    int64_t slot = __atomic_fetch_add(&n_next, 1, __ATOMIC_RELAXED);
-                                    next[slot] = f[j];
-                                }
+                if (fkey[gstart[gi]].side == 0) {
+                    /* Mark the remaining neighbours x of u = a; for each
+                     * F-edge (u,v) walk the remaining w in N(v) and x in
+                     * N(w): (w,x) closes [u,v,w,x]. */
+                    for (int64_t p = RU.ptr[a]; p < RU.ptr[a] + RU.len[a]; ++p) {
+                        ml[RU.nbr[p]] = stamp;
+                        el[RU.nbr[p]] = RU.eid[p];
+                    }
+                    for (int64_t j = gstart[gi]; j < gstart[gi + 1]; ++j) {
+                        int64_t e = fkey[j].e;
+                        int32_t u = a, v = col[e];
+                        for (int64_t q = RL.ptr[v]; q < RL.ptr[v] + RL.len[v]; ++q) {
+                            int32_t w = RL.nbr[q];
+                            if (w == u) continue;
+                            for (int64_t r = RU.ptr[w]; r < RU.ptr[w] + RU.len[w]; ++r) {
+                                int32_t x = RU.nbr[r];
+                                if (x == v || ml[x] != stamp) continue;
+                                f[0] = RL.eid[q]; f[1] = el[x]; f[2] = RU.eid[r];
+                                destroyed += destroy(e, f, in_f, s, level, next, &n_next);
                             }
                         }
                     }
-                    for (int64_t p = U.ptr[u]; p < U.ptr[u + 1]; ++p) ml[U.adj[p]] = -1;
+                    for (int64_t p = RU.ptr[a]; p < RU.ptr[a] + RU.len[a]; ++p) ml[RU.nbr[p]] = -1;
                 } else {
-                    /* Symmetric: mark the other remaining neighbours w of v,
-                     * then walk x in N(u) and w in N(x). */
-                    for (int64_t q = Ls.ptr[v]; q < Ls.ptr[v + 1]; ++q)
-                        if (Ls.eid[q] != e && alive[Ls.eid[q]]) { mu[Ls.adj[q]] = (int32_t)i; eu[Ls.adj[q]] = Ls.eid[q]; }
-                    for (int64_t p = U.ptr[u]; p < U.ptr[u + 1]; ++p) {
-                        int32_t x = U.adj[p];
-                        if (x == v || !alive[p]) continue;
-                        for (int64_t q = Ls.ptr[x]; q < Ls.ptr[x + 1]; ++q) {
-                            int32_t w = Ls.adj[q];
-                            int64_t ewx = Ls.eid[q];
-                            if (w == u || !alive[ewx] || mu[w] != (int32_t)i) continue;
-                            f[0] = eu[w]; f[1] = p; f[2] = ewx;
-                            int owner = 1;
-                            for (int j = 0; j < 3; ++j)
-                                if (in_f[f[j]] && f[j] < e) owner = 0;
-                            if (!owner) continue;
-                            ++destroyed;
-                            for (int j = 0; j < 3; ++j) {
-                                if (in_f[f[j]]) continue;
-                                int64_t old = __atomic_fetch_sub(&s[f[j]], 1, __ATOMIC_RELAXED);
-                                if (old > level && old - 1 <= level) {
-                                    int64_t slot = __atomic_fetch_add(&n_next, 1, __ATOMIC_RELAXED);
-                                    next[slot] = f[j];
-                                }
+                    /* Mirror: mark the remaining neighbours w of v = a; for
+                     * each F-edge (u,v) walk the remaining x in N(u) and w
+                     * in N(x). */
+                    for (int64_t q = RL.ptr[a]; q < RL.ptr[a] + RL.len[a]; ++q) {
+                        mu[RL.nbr[q]] = stamp;
+                        eu[RL.nbr[q]] = RL.eid[q];
+                    }
+                    for (int64_t j = gstart[gi]; j < gstart[gi + 1]; ++j) {
+                        int64_t e = fkey[j].e;
+                        int32_t u = urow[e], v = a;
+                        for (int64_t p = RU.ptr[u]; p < RU.ptr[u] + RU.len[u]; ++p) {
+                            int32_t x = RU.nbr[p];
+                            if (x == v) continue;
+                            for (int64_t q = RL.ptr[x]; q < RL.ptr[x] + RL.len[x]; ++q) {
+                                int32_t w = RL.nbr[q];
+                                if (w == u || mu[w] != stamp) continue;
+                                f[0] = eu[w]; f[1] = RU.eid[p]; f[2] = RL.eid[q];
+                                destroyed += destroy(e, f, in_f, s, level, next, &n_next);
                             }
                         }
                     }
-                    for (int64_t q = Ls.ptr[v]; q < Ls.ptr[v + 1]; ++q) mu[Ls.adj[q]] = -1;
+                    for (int64_t q = RL.ptr[a]; q < RL.ptr[a] + RL.len[a]; ++q) mu[RL.nbr[q]] = -1;
                 }
             }
         }
+        /* Remove F from the graph. */
         for (int64_t i = 0; i < n_front; ++i) {
-            alive[front[i]] = 0;
-            in_f[front[i]] = 0;
+            int64_t e = front[i];
+            alive[e] = 0;
+            in_f[e] = 0;
+            rows_remove(&RU, urow[e], e);
+            rows_remove(&RL, col[e], e);
         }
+        n_alive -= n_front;
         int64_t *tmp = front; front = next; next = tmp;
         n_front = n_next;
     }
@@ -395,7 +508,8 @@ int bto_bitruss(int32_t n_upper, int32_t n_lower, int64_t m,
     }
     free(mark_u); free(mark_l); free(meid_u); free(meid_l);
     free(s); free(alive); free(in_f); free(front); free(next); free(rest);
-    free(urow); free(hop_u); free(hop_l);
+    free(urow); free(hop_u); free(hop_l); free(fkey); free(gstart);
+    rows_free(&RU); rows_free(&RL);
     graph_free(&g);
     return 0;
 }

@@ -6,7 +6,14 @@ total and the generator version.  For the many-small-graphs pool the
 digest covers the concatenation of the per-graph arrays in pool order.
 Calls only `oracle` and the seeded generators.
 
-  python tests/golden/make_digests.py [uniform10k] [chunglu5m] [hub20m:sup] [pool:N] [big:N]
+  python tests/golden/make_digests.py [uniform10k] [chunglu5m] [hub20m] [hub20m:sup]
+                                      [hub20m:vsF] [pool:N] [big:N] [bigs:A-B]
+
+hub20m:vsF is the induced subgraph of the 20M-edge hub graph on a random
+fraction F of each layer's vertices (sampling seed 2027), the protocol of
+the paper's scalability experiments.  bigs:A-B adds request graphs A..B-1
+one at a time to the "bigs" entry (per-graph digests), so a long run can be
+stopped and resumed.
 """
 import hashlib
 import json
@@ -22,6 +29,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from paper_2001_06111_amd import synth  # noqa: E402
 
+VS_SEED = 2027
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "digests.json")
 
 
@@ -49,6 +57,33 @@ def main(args):
                             "levels": st["levels"], "rounds": st["rounds"],
                             "oracle_seconds": round(dt, 1), "oracle_threads": oracle.max_threads(),
                             "generator_version": synth.GENERATOR_VERSION}
+        elif a.startswith("hub20m:vs"):
+            frac = float(a.split(":vs")[1])
+            g = synth.vertex_sample(synth.plain_hub_20m(), frac, VS_SEED)
+            sup, bf, phi, st, dt = run(g)
+            data[g.name] = {"m": g.m, "n_upper": g.n_upper, "n_lower": g.n_lower,
+                            "butterflies": bf, "sup_sha256": sha(sup),
+                            "phi_sha256": sha(phi), "max_phi": int(phi.max()) if g.m else 0,
+                            "levels": st["levels"], "rounds": st["rounds"],
+                            "sample": {"of": "chunglu-100kx2M-m20M-hub", "fraction": frac,
+                                       "seed": VS_SEED},
+                            "oracle_seconds": round(dt, 1), "oracle_threads": oracle.max_threads(),
+                            "generator_version": synth.GENERATOR_VERSION}
+        elif a.startswith("bigs:"):
+            lo, hi = (int(x) for x in a.split(":")[1].split("-"))
+            ent = data.setdefault("bigs", {"per_graph": {}})
+            for j in range(lo, hi):
+                if str(j) in ent["per_graph"]:
+                    continue
+                g = synth.big_serving_graph(j)
+                sup, bf, phi, st, dt = run(g)
+                ent["per_graph"][str(j)] = {"m": g.m, "butterflies": bf, "sup_sha256": sha(sup),
+                                            "phi_sha256": sha(phi), "max_phi": int(phi.max()),
+                                            "oracle_seconds": round(dt, 1),
+                                            "oracle_threads": oracle.max_threads(),
+                                            "generator_version": synth.GENERATOR_VERSION}
+                json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+                print(f"big {j}: m={g.m} bf={bf} {dt:.0f}s", flush=True)
         elif a == "hub20m:sup":
             # Support counting only: the oracle's peel would take hours here.
             g = synth.plain_hub_20m()

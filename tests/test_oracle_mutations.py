@@ -14,12 +14,14 @@ from tests import graphs
 MUTATIONS = {
     "dropped_minus_one": ("s += (int64_t)cnt[w] - 1;", "s += (int64_t)cnt[w];"),
     "pairs_counted_twice": ("if (w > a) total += c * (c - 1) / 2;", "total += c * (c - 1) / 2;"),
-    "no_butterfly_owner": ("if (in_f[f[j]] && f[j] < e) owner = 0;", "if (in_f[f[j]] && f[j] < e) owner = 1;"),
+    # Every frontier edge of a butterfly acts on it, not only the smallest.
+    "no_butterfly_owner": ("if (in_f[f[j]] && f[j] < e) return 0;", "(void)0;"),
     "frontier_off_by_one": ("if (old > level && old - 1 <= level) {", "if (old > level && old - 1 <= level + 1) {"),
-    "removed_edge_counted": ("if (x == v || !alive[r] || ml[x] != (int32_t)i) continue;",
-                             "if (x == v || ml[x] != (int32_t)i) continue;"),
-    "decrement_by_two": ("__atomic_fetch_sub(&s[f[j]], 1, __ATOMIC_RELAXED);\n                                if (old > level && old - 1 <= level) {\n                                    int64_t slot = __atomic_fetch_add(&n_next, 1, __ATOMIC_RELAXED);\n                                    next[slot] = f[j];\n                                }\n                            }\n                        }\n                    }\n                    for (int64_t q",
-                         "__atomic_fetch_sub(&s[f[j]], 2, __ATOMIC_RELAXED);\n                                if (old > level && old - 2 <= level) {\n                                    int64_t slot = __atomic_fetch_add(&n_next, 1, __ATOMIC_RELAXED);\n                                    next[slot] = f[j];\n                                }\n                            }\n                        }\n                    }\n                    for (int64_t q"),
+    # A removed edge left in its upper row: walks then count butterflies
+    # through edges that are gone.
+    "removed_edge_counted": ("rows_remove(&RU, urow[e], e);", "(void)0;"),
+    "decrement_by_two": ("int64_t old = __atomic_fetch_sub(&s[f[j]], 1, __ATOMIC_RELAXED);\n        if (old > level && old - 1 <= level) {",
+                         "int64_t old = __atomic_fetch_sub(&s[f[j]], 2, __ATOMIC_RELAXED);\n        if (old > level && old - 2 <= level) {"),
 }
 
 
