@@ -94,6 +94,9 @@ typedef struct bt_stats {
                                  survivor taken one unit per removed wedge (no
                                  batch bloom processing, Section V-B); 0 where
                                  not counted */
+    int64_t wedge_visits;     /* live wedges of touched blooms visited by batch
+                                 bloom processing, summed over rounds: each such
+                                 visit lowers the wedge's two edges once */
 } bt_stats;
 
 /* Opaque device-resident BE-Index. */
@@ -297,12 +300,17 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
 /*
  * Serving engine with continuous batching (for request streams).
  *
- * bt_engine_create: `slots` worker slots (0: 1), each with its own HIP
- *   stream and workspace; `hbm_budget` bytes of device memory for requests
- *   in flight (0: half of the free memory); at most `max_batch` requests
- *   per batch (0: 1024).  The peel of a batch holds the whole GPU, so the
- *   peels of different slots take turns; more slots overlap only the other
- *   stages.
+ * bt_engine_create: `slots` worker slots (0: 2), each with its own HIP
+ *   stream and cached workspace; `hbm_budget` bytes of device memory for
+ *   the engine (0: half of the free memory); at most `max_batch` requests
+ *   per batch (0: 1024).  The peel of a batch holds most of the GPU, so the
+ *   peels of different slots take turns; a second slot counts and builds
+ *   the index of the next batch while one slot's batch peels.
+ *   Memory: the budget covers every slot's cached workspace plus what its
+ *   running batch may still allocate (the submit-time estimate, replaced by
+ *   the exact peel state once the batch's index is built); a slot frees its
+ *   cache, or asks idle slots to free theirs, when that is what keeps a
+ *   request out.
  * bt_engine_submit: queue one request.  Validates the graph and estimates
  *   its device memory on the device (index and peel state bounded through
  *   the wedge bound of Lemma 6, sum over edges of min(d(u), d(v)), plus
@@ -321,6 +329,9 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  * bt_engine_poll: moves up to `cap` completed (id, status) pairs to the
  *   caller's host arrays; *n_done receives how many.
  * bt_engine_drain: blocks until every submitted request has completed.
+ * bt_engine_memory: the budget, the bytes the slots' workspaces hold now,
+ *   the largest such sum so far, and the largest sum of held plus reserved
+ *   bytes so far (which admission keeps within the budget).
  * bt_engine_destroy: drains, stops the workers and frees the engine.
  */
 typedef struct bt_engine bt_engine;
@@ -335,7 +346,28 @@ bt_status bt_engine_drain(bt_engine *engine);
 /* Batches run, requests admitted and requests waiting (host pointers, nullable). */
 bt_status bt_engine_stats(bt_engine *engine, int64_t *batches, int64_t *admitted,
                           int64_t *queued);
+/* Host pointers, nullable. */
+bt_status bt_engine_memory(bt_engine *engine, int64_t *budget, int64_t *held,
+                           int64_t *peak_held, int64_t *peak_committed);
 void bt_engine_destroy(bt_engine *engine);
+
+/*
+ * Device-memory hook.  Every device buffer the library allocates (the
+ * cached workspaces of calls and engine slots, bt_index handles) is taken
+ * with alloc(bytes, ctx) and returned with free(ptr, bytes, ctx) on the
+ * device current at the call; alloc returns NULL on failure, and the call
+ * that needed the memory then fails with BT_ENOMEM, bt_last_error naming
+ * the byte count (the library stays usable).  Before a block goes back to
+ * free() the library waits for the device to finish its work, so a caching
+ * allocator may hand it out again at once.  Blocks are always returned to
+ * the hook that made them, even after the hook changes.  Both NULL
+ * restores hipMalloc / hipFree; one NULL without the other is BT_EINVAL.
+ * Not in the paper: lets a host framework (such as PyTorch's caching
+ * allocator) own the library's device memory.
+ */
+typedef void *(*bt_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*bt_free_fn)(void *ptr, size_t bytes, void *ctx);
+bt_status bt_set_allocator(bt_alloc_fn alloc, bt_free_fn free, void *ctx);
 
 /* Free the cached device workspace (it regrows on the next call). */
 void bt_release_workspace(void);

@@ -7,8 +7,10 @@ loudly when the library is missing: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -38,7 +40,7 @@ class bt_stats(ctypes.Structure):
         (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel",
                                       "ms_peel_kernel")] + [
         ("peel_launches", ctypes.c_int32), ("passes", ctypes.c_int32),
-        ("support_updates_unbatched", ctypes.c_int64)]
+        ("support_updates_unbatched", ctypes.c_int64), ("wedge_visits", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -64,7 +66,10 @@ EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_expor
             "bt_decompose_batch",
             "bt_bitruss_components", "bt_release_workspace", "bt_tune", "bt_tune_get",
             "bt_tune_set", "bt_tune_reset", "bt_tune_save", "bt_tune_load",
-            "bt_last_error", "bt_version"]
+            "bt_set_allocator", "bt_last_error", "bt_version"]
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 
 _lib = None
 
@@ -100,6 +105,8 @@ def load():
         L.bt_tune_save.argtypes = [ctypes.c_char_p]
         L.bt_tune_load.argtypes = [ctypes.c_char_p]
         L.bt_release_workspace.restype = None
+        L.bt_set_allocator.argtypes = [ALLOC_FN, FREE_FN, p]
+        L.bt_set_allocator.restype = ctypes.c_int
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
         for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
@@ -109,7 +116,72 @@ def load():
                      "bt_tune_reset", "bt_tune_save", "bt_tune_load"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
+        atexit.register(_teardown)
     return _lib
+
+
+def _teardown():
+    """At interpreter exit, in order: stop live engines, free the cached
+    workspace, forget tuned entries, restore the default allocator (a Python
+    hook must not be called once the interpreter is finalising)."""
+    L = _lib
+    if L is None:
+        return
+    for e in list(_ENGINES):
+        try:
+            e.bt_engine_destroy()
+        except Exception:
+            pass
+    try:
+        L.bt_release_workspace()
+        L.bt_tune_reset()
+        L.bt_set_allocator(ALLOC_FN(), FREE_FN(), None)
+    except Exception:
+        pass
+
+
+_ENGINES = weakref.WeakSet()
+# Every pair of Python callbacks ever installed: a block stays tied to the
+# hook that allocated it, so its callbacks must outlive the block.
+_CALLBACKS = []
+
+
+def bt_set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through Python callables:
+    alloc(nbytes) -> device address (int) or 0/None on failure, and
+    free(address, nbytes).  bt_set_allocator() restores hipMalloc/hipFree."""
+    L = load()
+    if alloc is None and free is None:
+        _check(L.bt_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def _a(nbytes, ctx):
+        try:
+            return alloc(int(nbytes)) or None
+        except Exception:
+            return None
+
+    def _f(ptr, nbytes, ctx):
+        try:
+            free(int(ptr), int(nbytes))
+        except Exception:
+            pass
+    cb = (ALLOC_FN(_a), FREE_FN(_f))
+    _CALLBACKS.append(cb)
+    _check(L.bt_set_allocator(cb[0], cb[1], None))
+
+
+def use_torch_allocator(device=None):
+    """Let PyTorch's caching allocator own the library's device memory."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+
+    def alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes, device=idx)
+
+    def free(ptr, nbytes):
+        torch.cuda.caching_allocator_delete(ptr)
+    bt_set_allocator(alloc, free)
 
 
 def _check(rc: int):
@@ -332,7 +404,7 @@ def bt_version() -> str:
 # --- serving engine ----------------------------------------------------------
 
 EXPORTED += ["bt_engine_create", "bt_engine_submit", "bt_engine_poll", "bt_engine_drain",
-             "bt_engine_stats", "bt_engine_destroy"]
+             "bt_engine_stats", "bt_engine_memory", "bt_engine_destroy"]
 
 
 def _engine_lib():
@@ -346,10 +418,11 @@ def _engine_lib():
         L.bt_engine_drain.argtypes = [p]
         L.bt_engine_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
+        L.bt_engine_memory.argtypes = [p] + [ctypes.POINTER(i64)] * 4
         L.bt_engine_destroy.argtypes = [p]
         L.bt_engine_destroy.restype = None
         for n in ("bt_engine_create", "bt_engine_submit", "bt_engine_poll", "bt_engine_drain",
-                  "bt_engine_stats"):
+                  "bt_engine_stats", "bt_engine_memory"):
             getattr(L, n).restype = ctypes.c_int
         L._engine_ready = True
     return L
@@ -359,13 +432,14 @@ class BtEngine:
     """bt_engine_* handle.  Keeps each request's graph and outputs alive until
     it completes; results are device tensors."""
 
-    def __init__(self, hbm_budget: int = 0, slots: int = 1, max_batch: int = 1024):
+    def __init__(self, hbm_budget: int = 0, slots: int = 0, max_batch: int = 1024):
         L = _engine_lib()
         self._h = ctypes.c_void_p(0)
         _check(L.bt_engine_create(int(hbm_budget), int(slots), int(max_batch),
                                   ctypes.byref(self._h)))
         self._live = {}
         self.results = {}
+        _ENGINES.add(self)
 
     def bt_engine_submit(self, g: DeviceGraph, req_id: int, want_sup: bool = False):
         L = _engine_lib()
@@ -405,6 +479,11 @@ class BtEngine:
         _check(_engine_lib().bt_engine_stats(self._h, ctypes.byref(b), ctypes.byref(a),
                                              ctypes.byref(q)))
         return {"batches": b.value, "admitted": a.value, "queued": q.value}
+
+    def bt_engine_memory(self):
+        v = [ctypes.c_int64(0) for _ in range(4)]
+        _check(_engine_lib().bt_engine_memory(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("budget", "held", "peak_held", "peak_committed"), (x.value for x in v)))
 
     def bt_engine_destroy(self):
         if self._h:

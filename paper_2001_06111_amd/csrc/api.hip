@@ -119,8 +119,8 @@ void build_all(const bt_csr &g, RankCSR &r, IndexArrays &ix, bool owned,
     make_tasks(r, t, ws, s);
     if (ev) ev->mark(1);
     alloc_index(r, ix, owned, ws, own);
-    BT_HIP(hipMemsetAsync(ix.supl, 0, sizeof(uint64_t) * (r.m + 1), s));
-    BT_HIP(hipMemsetAsync(ix.cursor, 0, sizeof(uint64_t) * 2, s));
+    zero_bytes(ix.supl, sizeof(uint64_t) * (r.m + 1), s);
+    zero_bytes(ix.cursor, sizeof(uint64_t) * 2, s);
     build_index(r, t, ix, ws, s);
     if (ev) ev->mark(2);
     check_butterfly_total(ix.supl, r.m, ix.butterflies, ws, s);
@@ -156,6 +156,7 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->peel_launches = (int32_t)pc.launches;
     stats->passes = 1;
     stats->support_updates_unbatched = pc.updates_unbatched;
+    stats->wedge_visits = pc.touched;
 }
 
 }  // namespace
@@ -222,8 +223,8 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
     ev.mark(1);
     uint64_t *supl = ws.get<uint64_t>("pc_supl", m + 1);
     int64_t *bf = ws.get<int64_t>("pc_bf", 2);
-    BT_HIP(hipMemsetAsync(supl, 0, sizeof(uint64_t) * (m + 1), s));
-    BT_HIP(hipMemsetAsync(bf, 0, sizeof(int64_t) * 2, s));
+    zero_bytes(supl, sizeof(uint64_t) * (m + 1), s);
+    zero_bytes(bf, sizeof(int64_t) * 2, s);
     count_support(r, t, supl, bf, s);
     check_butterfly_total(supl, m, bf, ws, s);
     if (sup_out && m) supl_to_sup(supl, sup_out, m, s);
@@ -262,6 +263,7 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
             if (pc.max_phi >= eps) tot.max_phi = std::max(tot.max_phi, pc.max_phi);
             tot.updates += pc.updates;
             tot.bloom_visits += pc.bloom_visits;
+            tot.touched += pc.touched;
             tot.kernel_ms += pc.kernel_ms;
             tot.launches += pc.launches;
             blooms += ix.n_b;
@@ -294,6 +296,7 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
         stats->ms_peel_kernel = (float)tot.kernel_ms;
         stats->peel_launches = (int32_t)tot.launches;
         stats->passes = passes;
+        stats->wedge_visits = tot.touched;
     }
 }
 
@@ -303,7 +306,8 @@ constexpr int64_t kMultiMaxEdges = int64_t(1) << 19;
 // build for the union, then one peel in which every graph has its own level.
 void decompose_union_impl(const bt_csr &u, const std::vector<int64_t> &off,
                           const Components &comps, int64_t *sup_out, int64_t *phi_out,
-                          bt_stats *stats, Workspace &ws, hipStream_t s) {
+                          bt_stats *stats, Workspace &ws, hipStream_t s,
+                          const SizedHook *on_sized = nullptr) {
     Events ev(stats != nullptr, s);
     ev.mark(0);
     RankCSR r;
@@ -319,6 +323,9 @@ void decompose_union_impl(const bt_csr &u, const std::vector<int64_t> &off,
     const char *mode = std::getenv("BT_BATCH_PEEL");
     const bool multi = ws.coop && off.size() > 2 && max_m <= kMultiMaxEdges &&
                        !(mode && std::strcmp(mode, "union") == 0);
+    if (on_sized && *on_sized)
+        (*on_sized)((int64_t)ws.bytes(),
+                    peel_state_bytes(u.m, ix.n_b, ix.n_w, (int64_t)off.size() - 1, multi));
     if (multi)
         peel_multi(r, ix, sup_out, phi_out, off, pc, ws, s);
     else
@@ -408,11 +415,13 @@ void add_stats(bt_stats &t, const bt_stats &s) {
     t.peel_launches += s.peel_launches;
     t.passes = std::max(t.passes, s.passes);
     t.support_updates_unbatched += s.support_updates_unbatched;
+    t.wedge_visits += s.wedge_visits;
 }
 
 // Graphs [a, b) as one union; splits the range if the union is too large.
 void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out,
-                 int64_t *const *phi_out, bt_stats *stats, Workspace &ws, hipStream_t s) {
+                 int64_t *const *phi_out, bt_stats *stats, Workspace &ws, hipStream_t s,
+                 const SizedHook *on_sized = nullptr) {
     std::vector<BatchEntry> tab(b - a);
     int64_t nu = 0, nl = 0, m = 0, max_span = 1;
     for (int32_t i = a; i < b; ++i) {
@@ -447,7 +456,7 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
     int64_t *phi_u = ws.get<int64_t>("batch_phi", m);
     BT_HIP(hipMemcpyAsync(dtab, tab.data(), sizeof(BatchEntry) * tab.size(),
                           hipMemcpyHostToDevice, s));
-    BT_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    zero_bytes(flags, sizeof(int32_t), s);
     fill_i64(row_ptr_u + nu, m, 1, s);
     const dim3 grid((unsigned)std::min<int64_t>(ceil_div(max_span, 256), 64),
                     (unsigned)std::min<int32_t>(b - a, 65535));
@@ -478,7 +487,8 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
     comps.u_off = dvoff + (b - a + 1);
     bt_stats st;
     try {
-        decompose_union_impl(u, off, comps, sup_u, phi_u, stats ? &st : nullptr, ws, s);
+        decompose_union_impl(u, off, comps, sup_u, phi_u, stats ? &st : nullptr, ws, s,
+                             on_sized);
     } catch (const Error &e) {
         if (e.status != BT_EOVERFLOW || !splittable) throw;
         const int32_t mid = a + (b - a) / 2;
@@ -500,7 +510,7 @@ constexpr int64_t kBatchEdges = int64_t(1) << 26;
 
 void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
-                          hipStream_t s) {
+                          hipStream_t s, const SizedHook *on_sized) {
     if (stats) std::memset(stats, 0, sizeof *stats);
     // Unions are cut from the graphs in decreasing edge count: a union peels
     // for as many rounds as its slowest graph needs, so the large graphs,
@@ -523,7 +533,9 @@ void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
         int32_t b = a;
         int64_t m = 0;
         while (b < n && (b == a || m + g2[(size_t)b].m <= kBatchEdges)) m += g2[(size_t)b++].m;
-        batch_range(g2.data(), a, b, sup_out ? s2.data() : nullptr, p2.data(), stats, ws, s);
+        // The size report is exact only when one union holds the whole batch.
+        batch_range(g2.data(), a, b, sup_out ? s2.data() : nullptr, p2.data(), stats, ws, s,
+                    a == 0 && b == n ? on_sized : nullptr);
         a = b;
     }
 }
@@ -570,6 +582,10 @@ void bt_release_workspace(void) {
     lib().ws.release();
 }
 
+bt_status bt_set_allocator(bt_alloc_fn alloc, bt_free_fn free, void *ctx) {
+    return guard([&] { set_allocator(alloc, free, ctx); });
+}
+
 bt_status bt_support(const bt_csr *g, int64_t *sup_out, int64_t *butterflies_out,
                      hipStream_t stream) {
     return guard([&] {
@@ -583,8 +599,8 @@ bt_status bt_support(const bt_csr *g, int64_t *sup_out, int64_t *butterflies_out
         make_tasks(r, t, ws, stream);
         uint64_t *supl = ws.get<uint64_t>("sup_supl", g->m + 1);
         int64_t *bf = ws.get<int64_t>("sup_bf", 2);
-        BT_HIP(hipMemsetAsync(supl, 0, sizeof(uint64_t) * (g->m + 1), stream));
-        BT_HIP(hipMemsetAsync(bf, 0, sizeof(int64_t) * 2, stream));
+        zero_bytes(supl, sizeof(uint64_t) * (g->m + 1), stream);
+        zero_bytes(bf, sizeof(int64_t) * 2, stream);
         count_support(r, t, supl, bf, stream);
         check_butterfly_total(supl, g->m, bf, ws, stream);
         supl_to_sup(supl, sup_out, g->m, stream);

@@ -80,6 +80,7 @@ private:
 
 void *device_alloc(size_t bytes);  // throws BT_ENOMEM with the size
 void device_free(void *p);
+void set_allocator(bt_alloc_fn a, bt_free_fn f, void *ctx);
 
 
 // ------------------------------------------------------ wave primitives
@@ -172,6 +173,8 @@ void radix_sort_u64_u32(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits,
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Sets `bytes` (a multiple of 4, at a 4-byte aligned address) to zero.
+void zero_bytes(void *p, size_t bytes, hipStream_t s);
 
 int grid_for(int64_t n, int block, int max_blocks = 1 << 20);
 

@@ -4,15 +4,27 @@
 // device-memory estimate taken at submit time.  Each worker slot owns a HIP
 // stream and a workspace; when a slot is free it picks a size class
 // (below 2^14 edges, below 2^19, larger) and admits, in arrival order,
-// queued requests of that class while their estimates fit the engine's
-// memory budget (less what the other slots hold), and decomposes them
-// together as one disjoint union; large requests a few at a time.  A batch
-// never mixes classes, so a small request never waits inside its batch for
-// a larger graph's peel.  The smallest class present goes first unless the
-// oldest request of a larger class has waited kLargeWaitS.  Requests that
-// arrive while batches run are admitted by the next free slot, so batches on
-// different slots overlap on the GPU.  Each result equals the plain
-// single-graph decomposition of the request.
+// queued requests of that class while the memory they may need fits the
+// engine's budget, and decomposes them together as one disjoint union;
+// large requests a few at a time.  A batch never mixes classes, so a small
+// request never waits inside its batch for a larger graph's peel.  The
+// smallest class present goes first unless the oldest request of a larger
+// class has waited kLargeWaitS.  Requests that arrive while batches run are
+// admitted by the next free slot: with two slots (the default) one slot
+// counts and builds the index of its batch on the device while the other
+// slot's batch peels.  Each result equals the plain single-graph
+// decomposition of the request.
+//
+// Memory.  A slot's workspace is cached between its batches, so the budget
+// covers what every slot holds plus what its running batch may still add:
+//   held[i]  bytes slot i's workspace holds (updated by slot i itself),
+//   res[i]   bytes its running batch may still allocate: the admission
+//            estimate (the wedge bound of Lemma 6) at first, then, once the
+//            batch's index is built, the exact peel state it still needs.
+// A slot admits a batch of estimate E only if sum over slots of held + res,
+// with its own res = E, stays within the budget; if its own cached
+// workspace is what stands in the way it frees it first, and idle slots
+// whose cached workspaces block an admission are asked to free theirs.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -56,6 +68,14 @@ constexpr int32_t kLargePerBatch = 4;
 // waited this long (so a steady stream of small requests cannot starve
 // larger ones).
 constexpr double kLargeWaitS = 10.0;
+constexpr int kDefaultSlots = 2;
+
+struct Slot {
+    int64_t held = 0;      // workspace bytes (written by the slot's own thread)
+    int64_t res = 0;       // bytes its running batch may still add
+    bool busy = false;
+    bool release = false;  // asked to free its cached workspace while idle
+};
 
 }  // namespace
 }  // namespace bt
@@ -69,8 +89,8 @@ struct bt_engine {
     std::condition_variable cv_work, cv_idle;
     std::deque<Request> queue;
     std::vector<Done> done;
-    int64_t reserved = 0;  // estimates of the batches now running
-    int64_t running = 0;   // requests now running
+    std::vector<Slot> slots;
+    int64_t running = 0;  // requests now running
     bool stop = false;
     std::vector<std::thread> workers;
     // submit-time estimates run on their own stream and workspace
@@ -79,10 +99,14 @@ struct bt_engine {
     hipStream_t est_stream = nullptr;
     int device = 0;
     int64_t batches = 0, admitted = 0;
+    int64_t peak_committed = 0;  // largest sum of held + res seen
+    int64_t peak_held = 0;       // largest sum of held seen
 
     void worker_loop(int slot);
     int pick_class() const;
     const Request *first_of(int cls) const;
+    int64_t committed_except(int s) const;
+    void note_peaks();
 };
 
 const Request *bt_engine::first_of(int cls) const {
@@ -105,43 +129,95 @@ int bt_engine::pick_class() const {
     return 0;
 }
 
+int64_t bt_engine::committed_except(int s) const {
+    int64_t t = 0;
+    for (size_t i = 0; i < slots.size(); ++i)
+        if ((int)i != s) t += slots[i].held + slots[i].res;
+    return t;
+}
+
+void bt_engine::note_peaks() {
+    int64_t c = 0, h = 0;
+    for (const Slot &sl : slots) {
+        c += sl.held + sl.res;
+        h += sl.held;
+    }
+    peak_committed = std::max(peak_committed, c);
+    peak_held = std::max(peak_held, h);
+}
+
 void bt_engine::worker_loop(int slot) {
     (void)hipSetDevice(device);
     hipStream_t s = nullptr;
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     Workspace ws;  // cooperative peels of different slots take turns (see peel.hip)
-    (void)slot;
     while (true) {
         std::vector<Request> batch;
-        int64_t bytes = 0;
+        int64_t bytes = 0, held0 = 0;
+        bool free_first = false;
         {
             std::unique_lock<std::mutex> lk(mu);
+            Slot &me = slots[(size_t)slot];
             int cls = 0;
             cv_work.wait(lk, [&] {
                 if (stop) return true;
+                if (me.release) return true;
                 if (queue.empty()) return false;
                 cls = pick_class();
-                return reserved + first_of(cls)->bytes <= budget;
+                const int64_t need = first_of(cls)->bytes;
+                const int64_t others = committed_except(slot);
+                if (others + need <= budget) return true;
+                // Idle slots whose cached workspaces stand in the way free them
+                // (woken only when a request to free is new, so idle slots do
+                // not wake each other in turn).
+                bool asked = false;
+                for (size_t i = 0; i < slots.size(); ++i)
+                    if ((int)i != slot && !slots[i].busy && slots[i].held > 0 &&
+                        !slots[i].release) {
+                        slots[i].release = true;
+                        asked = true;
+                    }
+                if (asked) cv_work.notify_all();
+                return false;
             });
             if (stop) break;  // destroy drains the queue before it stops workers
+            if (me.release) {  // idle and asked to free its cached workspace
+                me.release = false;
+                if (me.held > 0) {
+                    lk.unlock();
+                    ws.release();
+                    lk.lock();
+                    me.held = 0;
+                    note_peaks();
+                    cv_work.notify_all();
+                }
+                continue;
+            }
             // Admit requests of the chosen class in arrival order while the
-            // budget allows.
+            // budget allows (this slot's own cache may be freed to make room).
+            const int64_t others = committed_except(slot);
             const int32_t cap = cls == 2 ? std::min(max_batch, kLargePerBatch) : max_batch;
             for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < cap;) {
                 if (size_class_of(it->g.m) != cls) {
                     ++it;
                     continue;
                 }
-                if (reserved + bytes + it->bytes > budget) break;
+                if (others + bytes + it->bytes > budget) break;
                 bytes += it->bytes;
                 batch.push_back(*it);
                 it = queue.erase(it);
             }
-            reserved += bytes;
+            free_first = others + me.held + bytes > budget;
+            if (free_first) me.held = 0;  // freed below, before any allocation
+            held0 = me.held;
+            me.res = bytes;
+            me.busy = true;
             running += (int64_t)batch.size();
             batches += 1;
             admitted += (int64_t)batch.size();
+            note_peaks();
         }
+        if (free_first) ws.release();
         std::vector<bt_csr> gs;
         std::vector<int64_t *> sups, phis;
         for (auto &r : batch) {
@@ -149,10 +225,22 @@ void bt_engine::worker_loop(int slot) {
             sups.push_back(r.sup);
             phis.push_back(r.phi);
         }
+        // Once the index is built the peel's remaining need replaces what is
+        // left of the estimate, so other slots may admit against the
+        // difference.  The slot's commitment never grows past its admission
+        // (held0 + estimate); its real holdings are re-read at the end.
+        const SizedHook on_sized = [&](int64_t held, int64_t peel_bytes) {
+            std::lock_guard<std::mutex> lk(mu);
+            Slot &me = slots[(size_t)slot];
+            me.held = held;
+            me.res = std::max<int64_t>(0, std::min(peel_bytes, held0 + bytes - held));
+            note_peaks();
+            cv_work.notify_all();
+        };
         std::vector<Done> out;
         try {
             decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), nullptr,
-                                 ws, s);
+                                 ws, s, &on_sized);
             for (auto &r : batch) out.push_back(Done{r.id, BT_OK});
         } catch (const Error &) {
             // Isolate the failure: run the requests of the batch one by one.
@@ -170,9 +258,14 @@ void bt_engine::worker_loop(int slot) {
         } catch (...) {
             for (auto &r : batch) out.push_back(Done{r.id, BT_EDEVICE});
         }
+        const int64_t held_now = (int64_t)ws.bytes();
         {
             std::lock_guard<std::mutex> lk(mu);
-            reserved -= bytes;
+            Slot &me = slots[(size_t)slot];
+            me.held = held_now;
+            me.res = 0;
+            me.busy = false;
+            note_peaks();
             running -= (int64_t)batch.size();
             for (auto &d : out) done.push_back(d);
         }
@@ -204,7 +297,8 @@ bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
         E->max_batch = max_batch > 0 ? max_batch : 1024;
         BT_HIP(hipStreamCreateWithFlags(&E->est_stream, hipStreamNonBlocking));
         E->est_ws.coop = false;
-        const int n = slots > 0 ? slots : 1;
+        const int n = slots > 0 ? slots : kDefaultSlots;
+        E->slots.resize((size_t)n);
         for (int i = 0; i < n; ++i) E->workers.emplace_back(&bt_engine::worker_loop, E, i);
     } catch (const Error &e) {
         set_error(e.msg);
@@ -245,7 +339,7 @@ bt_status bt_engine_submit(bt_engine *E, const bt_csr *g, int64_t *sup_out, int6
         std::lock_guard<std::mutex> lk(E->mu);
         E->queue.push_back(r);
     }
-    E->cv_work.notify_one();
+    E->cv_work.notify_all();
     return BT_OK;
 }
 
@@ -285,6 +379,22 @@ bt_status bt_engine_stats(bt_engine *E, int64_t *batches, int64_t *admitted, int
     if (batches) *batches = E->batches;
     if (admitted) *admitted = E->admitted;
     if (queued) *queued = (int64_t)E->queue.size();
+    return BT_OK;
+}
+
+bt_status bt_engine_memory(bt_engine *E, int64_t *budget, int64_t *held, int64_t *peak_held,
+                           int64_t *peak_committed) {
+    if (!E) {
+        set_error("engine is NULL");
+        return BT_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(E->mu);
+    int64_t h = 0;
+    for (const Slot &sl : E->slots) h += sl.held;
+    if (budget) *budget = E->budget;
+    if (held) *held = h;
+    if (peak_held) *peak_held = E->peak_held;
+    if (peak_committed) *peak_committed = E->peak_committed;
     return BT_OK;
 }
 

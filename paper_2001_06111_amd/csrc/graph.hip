@@ -188,7 +188,7 @@ void validate_graph(const bt_csr &g, Workspace &ws, hipStream_t s) {
     const int64_t m = g.m;
     int64_t *hs = ws.host(4);
     int32_t *flags = ws.get<int32_t>("prep_flags", 4);
-    BT_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
+    zero_bytes(flags, 4 * sizeof(int32_t), s);
     if (nu > 0) {
         k_validate<<<grid_for((int64_t)nu * kWave, kBlock, 16384), kBlock, 0, s>>>(
             g.row_ptr, g.col, nu, nl, m, flags);
@@ -218,7 +218,7 @@ void prepare(const bt_csr &g, RankCSR &r, Workspace &ws, hipStream_t s,
 
     // Degrees and the priority order.
     int32_t *deg = ws.get<int32_t>("prep_deg", n);
-    BT_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (n > 0 ? n : 1), s));
+    zero_bytes(deg, sizeof(int32_t) * (n > 0 ? n : 1), s);
     if (nu > 0) {
         k_upper_degree<<<grid_for(nu, 256, 8192), 256, 0, s>>>(g.row_ptr, nu, nl, deg);
         BT_CHECK_LAUNCH();
@@ -363,7 +363,7 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
     RankCSR &r = const_cast<RankCSR &>(rc);
     if (!tune_valid(r.tp)) throw Error{BT_EINVAL, "invalid launch parameters"};
     int64_t *counts = ws.get<int64_t>("task_counts", 4);
-    BT_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(int64_t), s));
+    zero_bytes(counts, 4 * sizeof(int64_t), s);
     if (r.n > 0) {
         k_task_count<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(
             r.off, r.low, r.wpre, r.zbase, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk,
@@ -382,7 +382,7 @@ void make_tasks(const RankCSR &rc, TaskLists &t, Workspace &ws, hipStream_t s) {
     t.hash = ws.get<WedgeTask>("task_hash", t.n_hash);
     t.dense = ws.get<WedgeTask>("task_dense", t.n_dense);
     int32_t *cur = ws.get<int32_t>("task_cursor", 2);
-    BT_HIP(hipMemsetAsync(cur, 0, 2 * sizeof(int32_t), s));
+    zero_bytes(cur, 2 * sizeof(int32_t), s);
     if (r.n > 0 && (t.n_hash + t.n_dense) > 0) {
         k_task_fill<<<grid_for(r.n, 256, 4096), 256, 0, s>>>(
             r.off, r.low, r.wpre, r.zbase, r.n, r.n_lower, r.tp.hash_max_work, r.tp.dense_chunk,
@@ -428,7 +428,7 @@ int64_t footprint_bytes(const bt_csr &g, Workspace &ws, hipStream_t s) {
     int32_t *flags = ws.get<int32_t>("fp_flags", 4);
     int32_t *deg = ws.get<int32_t>("fp_deg", nl);
     unsigned long long *sum = ws.get<unsigned long long>("fp_sum", 1);
-    BT_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int32_t), s));
+    zero_bytes(flags, 4 * sizeof(int32_t), s);
     if (nu > 0) {
         k_validate<<<grid_for((int64_t)nu * kWave, kBlock, 16384), kBlock, 0, s>>>(
             g.row_ptr, g.col, nu, nl, m, flags);
@@ -438,8 +438,8 @@ int64_t footprint_bytes(const bt_csr &g, Workspace &ws, hipStream_t s) {
     BT_HIP(hipMemcpyAsync(hs, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
     if (*(int32_t *)hs != 0 || (nu == 0 && m != 0)) throw Error{BT_EINVAL, "malformed graph"};
-    BT_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * (nl > 0 ? nl : 1), s));
-    BT_HIP(hipMemsetAsync(sum, 0, sizeof(unsigned long long), s));
+    zero_bytes(deg, sizeof(int32_t) * (nl > 0 ? nl : 1), s);
+    zero_bytes(sum, sizeof(unsigned long long), s);
     if (m > 0) {
         k_lower_degree<<<grid_for(m, 256, 16384), 256, 0, s>>>(g.col, m, deg);
         BT_CHECK_LAUNCH();

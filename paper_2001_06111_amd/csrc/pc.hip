@@ -115,7 +115,7 @@ int32_t pc_kmax(const uint64_t *supl, int64_t m, int32_t *sup0, Workspace &ws, h
     int64_t lo = 0, hi = std::min<int64_t>(m, INT_MAX);
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) / 2;
-        BT_HIP(hipMemsetAsync(cnt, 0, sizeof *cnt, s));
+        zero_bytes(cnt, sizeof *cnt, s);
         k_count_ge<<<grid_for(m, kB, 4096), kB, 0, s>>>(sup0, m, (int32_t)mid, cnt);
         BT_CHECK_LAUNCH();
         BT_HIP(hipMemcpyAsync(h, cnt, sizeof *cnt, hipMemcpyDeviceToHost, s));
@@ -145,7 +145,7 @@ int64_t pc_subgraph(const bt_csr &g, const int32_t *sup0, int32_t eps, const int
     sg.orig = ws.get<int32_t>("pc_orig", ms);
     sg.fixed = ws.get<int32_t>("pc_fixed", ms);
     unsigned long long *n_open = ws.get<unsigned long long>("pc_open", 1);
-    BT_HIP(hipMemsetAsync(n_open, 0, sizeof *n_open, s));
+    zero_bytes(n_open, sizeof *n_open, s);
     k_sub_rows<<<grid_for((int64_t)g.n_upper + 1, kB, 16384), kB, 0, s>>>(g.row_ptr, g.n_upper,
                                                                           pos, sg.row_ptr);
     BT_CHECK_LAUNCH();

@@ -278,7 +278,7 @@ __device__ __forceinline__ void phase_a_work(const PeelArgs &P, int p, const Rou
 // round; across the threshold, adds it to the active set.
 __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Round &R,
                                              int64_t wid, int64_t nwaves, bool lead, u64 &upd,
-                                             u64 &visits, u64 &unb) {
+                                             u64 &visits, u64 &unb, u64 &touch) {
     PeelCtl *C = P.ctl;
     const int q = p ^ 1;
     const int32_t level = R.level;
@@ -362,6 +362,7 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
         put_front(P, q, base[0] + k1, eb, lo2, hi2, k2, level);
         if (a1) st(&P.act[cur][base[1]], ea);
         if (a2) st(&P.act[cur][base[1] + (a1 ? 1 : 0)], eb);
+        touch += live ? 1 : 0;
         const int32_t per = P.unit ? c : 1;  // decrements per survivor edge
         upd += (u64)((da ? per : 0) + (db ? per : 0));
         // Without batch bloom processing each of the C kills would lower each
@@ -380,14 +381,17 @@ __device__ __forceinline__ void phase_b_work(const PeelArgs &P, int p, const Rou
 }
 
 // Adds per-lane statistics to the control block (one atomic per wave).
-__device__ __forceinline__ void flush_stats(PeelCtl *C, u64 upd, u64 visits, u64 unb = 0) {
+__device__ __forceinline__ void flush_stats(PeelCtl *C, u64 upd, u64 visits, u64 unb = 0,
+                                            u64 touch = 0) {
     upd = wave_sum(upd);
     visits = wave_sum(visits);
     unb = wave_sum(unb);
+    touch = wave_sum(touch);
     if (lane_id() == 0) {
         if (upd) atomicAdd(&C->updates.v, upd);
         if (visits) atomicAdd(&C->bloom_visits.v, visits);
         if (unb) atomicAdd(&C->unbatched.v, unb);
+        if (touch) atomicAdd(&C->touched.v, touch);
     }
 }
 
@@ -431,11 +435,11 @@ __global__ __launch_bounds__(kBlock) void k_phase_b(PeelArgs P, int p) {
     __syncthreads();
     if (!s_ok) return;
     const Round R = sR;
-    u64 upd = 0, visits = 0, unb = 0;
+    u64 upd = 0, visits = 0, unb = 0, touch = 0;
     phase_b_work(P, p, R, (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x,
                  (int64_t)gridDim.x * kWavesPerBlock, blockIdx.x == 0 && threadIdx.x == 0, upd,
-                 visits, unb);
-    flush_stats(C, upd, visits, unb);
+                 visits, unb, touch);
+    flush_stats(C, upd, visits, unb, touch);
 }
 
 // --- persistent cooperative kernel: rounds separated by grid barriers ---
@@ -642,7 +646,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     // registers (which would push the kernel past 128 VGPRs into spills).
     __shared__ u64 t[5], acc[6];
     __shared__ LeadStats L;
-    u64 upd = 0, visits = 0, unb = 0;
+    u64 upd = 0, visits = 0, unb = 0, touch = 0;
     if (lead) {
         L.load(C);
         for (int k = 0; k < 6; ++k) acc[k] = 0;
@@ -677,7 +681,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         if (!s_ok) break;
         R.ntc = sR.ntc;
         if (prof && lead) t[2] = wall_clock64();
-        phase_b_work(P, p, R, wid, nwaves, lead, upd, visits, unb);
+        phase_b_work(P, p, R, wid, nwaves, lead, upd, visits, unb, touch);
         if (prof && lead) t[3] = wall_clock64();
         drain_memory();
         __syncthreads();
@@ -693,13 +697,17 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
             if (R.mode == kGather) {
                 acc[4] += t[2] - t[0];
                 acc[5] += 1;
+            } else {
+                const int bnf = 63 - __clzll(R.nf | 1), bntc = 63 - __clzll(R.ntc | 1);
+                st(&C->time_nf[bnf], ld(&C->time_nf[bnf]) + (t[4] - t[0]));
+                st(&C->time_ntc[bntc], ld(&C->time_ntc[bntc]) + (t[4] - t[2]));
             }
         }
         p ^= 1;
     }
     if (s_fail) break;
     }
-    flush_stats(C, upd, visits, unb);
+    flush_stats(C, upd, visits, unb, touch);
     if (lead) {
         L.store(C);
         st(&C->pad, p);
@@ -844,8 +852,8 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     BT_CHECK_LAUNCH();
     k_init_alive<<<grid_for(words, 256, 16384), 256, 0, s>>>(ix.cursor, P.alive);
     BT_CHECK_LAUNCH();
-    BT_HIP(hipMemsetAsync(P.bc, 0, sizeof(int32_t) * nb, s));
-    BT_HIP(hipMemsetAsync(P.bdone, 0, sizeof(int32_t) * nb, s));
+    zero_bytes(P.bc, sizeof(int32_t) * nb, s);
+    zero_bytes(P.bdone, sizeof(int32_t) * nb, s);
     PeelCtl init{};
     init.gmin[0] = init.gmin[1] = INT_MAX;
     BT_HIP(hipMemcpyAsync(P.ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
@@ -861,7 +869,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     const char *gv = std::getenv("BT_PEEL_GRAPH");
     const bool use_graph = !(gv && std::atoi(gv) == 0);
     GridBar *bar = ws.get<GridBar>("peel_bar", 1);
-    BT_HIP(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
+    zero_bytes(bar, sizeof(GridBar), s);
     int pblocks = 0;
     if (persistent) {
         int dev = 0, cus = 0, occ = 0;
@@ -925,7 +933,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             // minimum support, histogram supports above it, pick T so that
             // the set holds a few percent of the remaining edges.
             const int nxt = cur < 0 ? 0 : cur ^ 1;
-            BT_HIP(hipMemsetAsync(rs, 0, sizeof(u64) * 40, s));
+            zero_bytes(rs, sizeof(u64) * 40, s);
             fill_i32(reinterpret_cast<int32_t *>(rs + 1), INT_MAX, 1, s);
             k_refill_compact<<<grid_for(n_all, kBlock, 4096), kBlock, 0, s>>>(
                 cur < 0 ? nullptr : glist[cur], n_all, P.phi, P.sup, glist[nxt], rs,
@@ -956,7 +964,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
                 }
             }
             thresh = std::max<int64_t>(thresh, std::min<int64_t>((int64_t)mn + 1, INT_MAX));
-            BT_HIP(hipMemsetAsync(&P.ctl->na[0].v, 0, sizeof(u64), s));
+            zero_bytes(&P.ctl->na[0].v, sizeof(u64), s);
             k_refill_gather<<<grid_for(n_all, kBlock, 4096), kBlock, 0, s>>>(
                 glist[cur], n_all, P.sup, (int32_t)thresh, P.act[0], &P.ctl->na[0].v);
             BT_CHECK_LAUNCH();
@@ -1007,6 +1015,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     pc.updates = (int64_t)hc->updates.v;
     pc.bloom_visits = (int64_t)hc->bloom_visits.v;
     pc.updates_unbatched = pc.updates + (int64_t)hc->unbatched.v;
+    pc.touched = (int64_t)hc->touched.v;
     if (std::getenv("BT_PEEL_PROFILE"))
         std::fprintf(stderr, "[peel] rounds %llu  block0 us: phaseA %.0f bar1 %.0f phaseB %.0f bar2 %.0f; gather rounds %llu phaseA+bar1 %.0f\n",
                      hc->rounds, hc->prof[0] / 100.0, hc->prof[1] / 100.0, hc->prof[2] / 100.0,
@@ -1019,6 +1028,12 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
         std::fprintf(stderr, "\n[peel] bloom items log2 histogram:");
         for (int b = 0; b < 32; ++b)
             if (hc->hist_ntc[b]) std::fprintf(stderr, " %d:%llu", b, hc->hist_ntc[b]);
+        std::fprintf(stderr, "\n[peel] normal-round us by log2 frontier items:");
+        for (int b = 0; b < 32; ++b)
+            if (hc->time_nf[b]) std::fprintf(stderr, " %d:%.0f", b, hc->time_nf[b] / 100.0);
+        std::fprintf(stderr, "\n[peel] phase-B+barrier us by log2 bloom items:");
+        for (int b = 0; b < 32; ++b)
+            if (hc->time_ntc[b]) std::fprintf(stderr, " %d:%.0f", b, hc->time_ntc[b] / 100.0);
         std::fprintf(stderr, "\n");
     }
     k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);

@@ -58,6 +58,7 @@ struct PeelCtl {
     Counter updates;
     Counter bloom_visits;
     Counter unbatched;  // extra decrements if survivors took one per kill (no bloom batching)
+    Counter touched;    // live wedges visited in phase B (survivors of touched blooms)
     // Round state, indexed by round parity.  Round r's entry is derived
     // from round r - 1's final counters (every block computes the same
     // values; block 0 stores them for round r + 1).
@@ -77,6 +78,9 @@ struct PeelCtl {
     Counter push_twin[2], push_surv[2];
     u64 twin_only_rounds, twin_pushes, surv_pushes;
     u64 hist_nf[32], hist_ntc[32];
+    // Block-0 clock ticks of whole rounds by log2 of their frontier items,
+    // and of phase B by log2 of its bloom items.
+    u64 time_nf[32], time_ntc[32];
 };
 
 struct alignas(16) FrontItem {

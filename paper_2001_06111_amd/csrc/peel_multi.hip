@@ -52,6 +52,7 @@ struct alignas(16) GatherItem {
 struct MultiCtl {
     Counter nf[2], ntc[2], ngth[2];
     Counter updates, bloom_visits;
+    Counter touched;  // live wedges visited in phase B
     Counter left;  // graphs not done
     u64 rounds;
     u64 prof[5];   // BT_PEEL_PROFILE=1: block-0 clock ticks (decide, A, bar, B, bar)
@@ -268,7 +269,7 @@ __device__ __forceinline__ void multi_phase_a(const PeelArgs &P, const MultiArgs
 
 __device__ __forceinline__ void multi_phase_b(const PeelArgs &P, const MultiArgs &M, int p,
                                               u64 ntc, int64_t wid, int64_t nwaves, u64 &upd,
-                                              u64 &visits) {
+                                              u64 &visits, u64 &touch) {
     MultiCtl *C = M.ctl;
     const int q = p ^ 1;
     for (int64_t i = wid; i < (int64_t)ntc; i += nwaves) {
@@ -319,6 +320,7 @@ __device__ __forceinline__ void multi_phase_b(const PeelArgs &P, const MultiArgs
         if (f1) set_front_flag(M, g1, q);
         if (f2) set_front_flag(M, g2, q);
         upd += live ? 2 : 0;
+        touch += live ? 1 : 0;
         if (live && kn <= 1) atomicAnd(&P.alive[w >> 5], ~(1u << (w & 31)));
         if (last) {
             st(&P.bk[b], kn);
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M,
     const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
     const int64_t tid = wid * kWave + lane_id();
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    u64 upd = 0, visits = 0;
+    u64 upd = 0, visits = 0, touch = 0;
     if (threadIdx.x == 0) {
         s_left = ld(&C->left.v);
         s_nf = ld(&C->nf[0].v);
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M,
             st(&C->nf[p].v, (u64)0);
             st(&C->ngth[p].v, (u64)0);
         }
-        multi_phase_b(P, M, p, s_ntc, wid, nwaves, upd, visits);
+        multi_phase_b(P, M, p, s_ntc, wid, nwaves, upd, visits, touch);
         drain_memory();
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -391,9 +393,11 @@ __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M,
     }
     upd = wave_sum(upd);
     visits = wave_sum(visits);
+    touch = wave_sum(touch);
     if (lane_id() == 0) {
         if (upd) atomicAdd(&C->updates.v, upd);
         if (visits) atomicAdd(&C->bloom_visits.v, visits);
+        if (touch) atomicAdd(&C->touched.v, touch);
     }
     if (lead) st(&C->rounds, (u64)r);
 }
@@ -417,6 +421,22 @@ __global__ void k_multi_init(const int64_t *off, int32_t ng, int32_t *gid) {
 }
 
 }  // namespace
+
+int64_t peel_state_bytes(int64_t m, int64_t n_b, int64_t n_w, int64_t graphs, bool multi) {
+    const int64_t nb = n_b > 0 ? n_b : 1;
+    const int64_t words = (n_w + 31) / 32 + 1;
+    const int64_t max_tc = nb + n_w / kWedgeChunk + 1;
+    const int64_t max_front = m + 2 * n_w / kLinkChunk + 1;
+    const int64_t max_gth = m / kGatherChunk + graphs + 1;
+    // Buffers of peel() or of peel_multi().
+    const int64_t shared = 4 * m * 2 + 4 * words + 4 * nb * 2 + 16 * max_front * 2;
+    const int64_t single = 16 * max_tc * 2 + 4 * m * 4 + 4096;
+    const int64_t per_graph = 64 * graphs + 4 * m + 16 * max_tc * 2 + 16 * max_gth * 2 +
+                              8 * (graphs + 1) + 4096;
+    const int64_t buffers = 24;  // each rounded up to 256 bytes
+    const int64_t t = shared + (multi ? per_graph : single) + 256 * buffers;
+    return t + t / 8;
+}
 
 void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
                 const std::vector<int64_t> &off, PeelCounters &pc, Workspace &ws, hipStream_t s) {
@@ -464,8 +484,8 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
     BT_CHECK_LAUNCH();
     k_init_alive<<<grid_for(words, 256, 16384), 256, 0, s>>>(ix.cursor, P.alive);
     BT_CHECK_LAUNCH();
-    BT_HIP(hipMemsetAsync(P.bc, 0, sizeof(int32_t) * nb, s));
-    BT_HIP(hipMemsetAsync(P.bdone, 0, sizeof(int32_t) * nb, s));
+    zero_bytes(P.bc, sizeof(int32_t) * nb, s);
+    zero_bytes(P.bdone, sizeof(int32_t) * nb, s);
     BT_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (ng + 1), hipMemcpyHostToDevice, s));
     k_multi_init<<<std::min(ng, 4096), 256, 0, s>>>(doff, ng, gid);
     BT_CHECK_LAUNCH();
@@ -491,7 +511,7 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
     mc.left.v = (u64)left;
     BT_HIP(hipMemcpyAsync(M.ctl, &mc, sizeof mc, hipMemcpyHostToDevice, s));
     GridBar *bar = ws.get<GridBar>("peel_bar", 1);
-    BT_HIP(hipMemsetAsync(bar, 0, sizeof(GridBar), s));
+    zero_bytes(bar, sizeof(GridBar), s);
     int dev = 0, cus = 0, occ = 0;
     BT_HIP(hipGetDevice(&dev));
     BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -530,6 +550,7 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
     pc.rounds = (int64_t)hc.rounds;
     pc.updates = (int64_t)hc.updates.v;
     pc.bloom_visits = (int64_t)hc.bloom_visits.v;
+    pc.touched = (int64_t)hc.touched.v;
     if (prof)
         std::fprintf(stderr, "[multi] rounds %llu block0 us: decide %.0f phaseA %.0f bar1 %.0f phaseB+bar2 %.0f\n",
                      hc.rounds, hc.prof[0] / 100.0, hc.prof[1] / 100.0, hc.prof[2] / 100.0,
@@ -540,7 +561,7 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
     k_phi_out<<<grid_for(m, 256, 16384), 256, 0, s>>>(P.phi, phi_out, m);
     BT_CHECK_LAUNCH();
     unsigned long long *mx = ws.get<unsigned long long>("pm_max", 1);
-    BT_HIP(hipMemsetAsync(mx, 0, sizeof *mx, s));
+    zero_bytes(mx, sizeof *mx, s);
     k_max_phi<<<grid_for(m, 256, 4096), 256, 0, s>>>(P.phi, m, mx);
     BT_CHECK_LAUNCH();
     unsigned long long hmx = 0;

@@ -1,6 +1,7 @@
 // pipeline.h - stages of the hot path and the device views they share.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "common.h"
@@ -134,6 +135,7 @@ void build_index(const RankCSR &r, const TaskLists &t, IndexArrays &ix, Workspac
 struct PeelCounters {
     int64_t levels = 0, rounds = 0, max_phi = 0, updates = 0, bloom_visits = 0;
     int64_t updates_unbatched = 0;  // the same peel without batch bloom processing
+    int64_t touched = 0;            // live wedges visited in phase B (L_touch)
     double kernel_ms = 0;  // HIP-event time of the peel kernel launches
     int64_t launches = 0;
 };
@@ -170,9 +172,17 @@ constexpr double kAutoPcTau = 0.05;
 TuneParams autotune(const bt_csr *gs, int32_t n, uint32_t what, Workspace &ws, hipStream_t s);
 // Device time of the index build alone (priority order, sweeps, links).
 float index_build_ms(const bt_csr &g, Workspace &ws, hipStream_t stream);
+// Called when a batch that forms a single union has its index built: the
+// bytes the workspace holds now, and at most how many the peel still adds.
+using SizedHook = std::function<void(int64_t held, int64_t peel_bytes)>;
 void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
                           int64_t *const *phi_out, bt_stats *stats, Workspace &ws,
-                          hipStream_t s);
+                          hipStream_t s, const SizedHook *on_sized = nullptr);
+// Device bytes of peel state for a graph (or union of `graphs` graphs) with
+// m edges and an index of n_b blooms and n_w wedges, for the per-graph-level
+// peel (multi) or the shared-level one; an upper bound, workspace growth
+// slack included.
+int64_t peel_state_bytes(int64_t m, int64_t n_b, int64_t n_w, int64_t graphs, bool multi);
 // BiT-PC steps (pc.hip).  A pass's subgraph G_{>=eps}: the edges of g with
 // support >= eps in g, in g's order; orig maps them back, fixed marks those
 // whose bitruss numbers earlier passes fixed, open counts the others.

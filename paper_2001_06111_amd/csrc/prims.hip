@@ -1,4 +1,8 @@
-// prims.hip - device-wide scans, stable radix sort, fills, workspace.
+// prims.hip - device-wide scans, stable radix sort, fills, workspace, the
+// device-memory allocator hook.
+
+#include <mutex>
+#include <unordered_map>
 
 #include "common.h"
 
@@ -17,21 +21,84 @@ extern "C" const char *bt_last_error(void) { return bt::g_last_error.c_str(); }
 namespace bt {
 
 // --------------------------------------------------------- memory
+// Every device buffer of the library comes from device_alloc: hipMalloc, or
+// the caller's hook (bt_set_allocator).  Each live block remembers the hook
+// that made it, so a block is always returned to its own allocator even if
+// the hook changes meanwhile.
+
+namespace {
+struct Hook {
+    bt_alloc_fn alloc = nullptr;
+    bt_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+struct Block {
+    Hook hook;
+    size_t bytes;
+};
+std::mutex &alloc_mu() {
+    static std::mutex *m = new std::mutex();  // never destroyed: outlives static teardown
+    return *m;
+}
+Hook g_hook;
+std::unordered_map<void *, Block> &live_blocks() {
+    static auto *m = new std::unordered_map<void *, Block>();
+    return *m;
+}
+}  // namespace
+
+void set_allocator(bt_alloc_fn a, bt_free_fn f, void *ctx) {
+    if ((a == nullptr) != (f == nullptr))
+        throw Error{BT_EINVAL, "bt_set_allocator needs both functions or neither"};
+    std::lock_guard<std::mutex> lk(alloc_mu());
+    g_hook = Hook{a, f, ctx};
+}
 
 void *device_alloc(size_t bytes) {
     void *p = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error{BT_ENOMEM, "device allocation of " + std::to_string(bytes) +
-                                   " bytes failed: " + hipGetErrorString(e)};
+    Hook h;
+    {
+        std::lock_guard<std::mutex> lk(alloc_mu());
+        h = g_hook;
     }
+    if (h.alloc) {
+        p = h.alloc(bytes, h.ctx);
+        if (!p)
+            throw Error{BT_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                       " bytes failed (allocator hook returned NULL)"};
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{BT_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                       " bytes failed: " + hipGetErrorString(e)};
+        }
+    }
+    std::lock_guard<std::mutex> lk(alloc_mu());
+    live_blocks()[p] = Block{h, bytes};
     return p;
 }
 
 void device_free(void *p) {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    Block b{};
+    {
+        std::lock_guard<std::mutex> lk(alloc_mu());
+        auto it = live_blocks().find(p);
+        if (it != live_blocks().end()) {
+            b = it->second;
+            live_blocks().erase(it);
+        }
+    }
+    if (b.hook.free) {
+        // A hook may hand the block out again at once (a caching allocator),
+        // so no kernel of the library may still use it.
+        (void)hipDeviceSynchronize();
+        b.hook.free(p, b.bytes, b.hook.ctx);
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 Workspace::~Workspace() { release(); }
@@ -115,6 +182,15 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     k_fill<uint32_t><<<grid_for(n, 256, 8192), 256, 0, s>>>(p, v, n);
     BT_CHECK_LAUNCH();
+}
+
+// Clearing by a kernel rather than hipMemsetAsync: a caller may capture the
+// library's work in a HIP graph, where memset nodes are avoided.
+void zero_bytes(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(p) % 4 != 0)
+        throw Error{BT_EDEVICE, "zero_bytes: size or address not a multiple of 4"};
+    fill_u32(static_cast<uint32_t *>(p), 0u, (int64_t)(bytes / 4), s);
 }
 
 // ------------------------------------------------------------ scan

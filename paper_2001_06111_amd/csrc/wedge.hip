@@ -323,7 +323,7 @@ template <bool DENSE, bool INDEX>
 void launch_wedge(const WedgeArgs &A, const WedgeTask *tasks, int64_t n, int wg_per_cu,
                   hipStream_t s) {
     if (n <= 0) return;
-    BT_HIP(hipMemsetAsync(A.queue, 0, sizeof(int64_t), s));
+    zero_bytes(A.queue, sizeof(int64_t), s);
     int dev = 0, cus = 0;
     BT_HIP(hipGetDevice(&dev));
     BT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -357,7 +357,7 @@ void check_butterfly_total(const uint64_t *supl, int64_t m, const int64_t *butte
                            Workspace &ws, hipStream_t s) {
     if (m <= 0) return;
     unsigned long long *tot = ws.get<unsigned long long>("bf_check", 1);
-    BT_HIP(hipMemsetAsync(tot, 0, sizeof *tot, s));
+    zero_bytes(tot, sizeof *tot, s);
     k_support_total<<<grid_for(m, 256, 4096), 256, 0, s>>>(supl, m, tot);
     BT_CHECK_LAUNCH();
     int64_t *h = ws.host(2);

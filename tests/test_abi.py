@@ -70,6 +70,10 @@ def test_argument_errors_without_gpu():
         (lambda: L.bt_tune(ctypes.byref(_csr()), 0, 3, None, None), binding.BT_EINVAL),
         (lambda: L.bt_tune(ctypes.byref(_csr()), 1, 8, None, None), binding.BT_EINVAL),
         (lambda: L.bt_tune_get(0, -1, None), binding.BT_EINVAL),
+        (lambda: L.bt_set_allocator(binding.ALLOC_FN(), binding.FREE_FN(lambda p, n, c: None),
+                                    None), binding.BT_EINVAL),
+        (lambda: L.bt_set_allocator(binding.ALLOC_FN(lambda n, c: None), binding.FREE_FN(),
+                                    None), binding.BT_EINVAL),
     ]
     for i, (call, want) in enumerate(cases):
         rc = call()
