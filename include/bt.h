@@ -369,6 +369,22 @@ typedef void *(*bt_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*bt_free_fn)(void *ptr, size_t bytes, void *ctx);
 bt_status bt_set_allocator(bt_alloc_fn alloc, bt_free_fn free, void *ctx);
 
+/*
+ * bt_support without allocating: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, results and errors as bt_support.
+ * Its scratch memory is a static device array of 64 MiB that every GPU the
+ * library runs on holds until the process ends; no hipMalloc, hipFree or
+ * allocator hook is called.  Graphs with more than 2^18 edges or more than
+ * 2^18 vertices (n_upper + n_lower) fail with BT_EOVERFLOW.  Calls on one
+ * device share that array: the library serialises them within a process
+ * (each call leaves the array to the next), so work of two calls that
+ * overlapped on one GPU, from different processes' copies aside, would
+ * race; the call returns only after its work on `stream` is complete.
+ */
+bt_status bt_support_noalloc(const bt_csr *g, int64_t *sup_out, int64_t *butterflies_out,
+                             hipStream_t stream);
+
 /* Free the cached device workspace (it regrows on the next call). */
 void bt_release_workspace(void);
 

@@ -66,7 +66,7 @@ EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_expor
             "bt_decompose_batch",
             "bt_bitruss_components", "bt_release_workspace", "bt_tune", "bt_tune_get",
             "bt_tune_set", "bt_tune_reset", "bt_tune_save", "bt_tune_load",
-            "bt_set_allocator", "bt_last_error", "bt_version"]
+            "bt_set_allocator", "bt_support_noalloc", "bt_last_error", "bt_version"]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -83,6 +83,7 @@ def load():
         L = ctypes.CDLL(LIB_PATH)
         p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.bt_support.argtypes = [ctypes.POINTER(bt_csr), p, ctypes.POINTER(i64), p]
+        L.bt_support_noalloc.argtypes = [ctypes.POINTER(bt_csr), p, ctypes.POINTER(i64), p]
         L.bt_index_build.argtypes = [ctypes.POINTER(bt_csr), ctypes.POINTER(p), p]
         L.bt_index_info_get.argtypes = [p, ctypes.POINTER(bt_index_info)]
         L.bt_index_export.argtypes = [p, p, p, p, p, p, p]
@@ -109,7 +110,7 @@ def load():
         L.bt_set_allocator.restype = ctypes.c_int
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
-        for name in ("bt_support", "bt_index_build", "bt_index_info_get", "bt_index_export",
+        for name in ("bt_support", "bt_support_noalloc", "bt_index_build", "bt_index_info_get", "bt_index_export",
                      "bt_decompose", "bt_decompose_variant", "bt_decompose_pc",
                      "bt_decompose_batch",
                      "bt_bitruss_components", "bt_tune", "bt_tune_get", "bt_tune_set",
@@ -231,6 +232,18 @@ def bt_support(g: DeviceGraph, stream=None):
     bf = ctypes.c_int64(0)
     c = g.csr()
     _check(L.bt_support(ctypes.byref(c), _ptr(sup), ctypes.byref(bf), _stream(stream)))
+    return sup, int(bf.value)
+
+
+def bt_support_noalloc(g: DeviceGraph, out_sup: torch.Tensor | None = None, stream=None):
+    """bt_support from static scratch: (supports, total butterflies).  Pass
+    `out_sup` (int64[m] on the device) for a call that allocates nothing."""
+    L = load()
+    sup = out_sup if out_sup is not None else torch.empty(g.m, dtype=torch.int64,
+                                                          device=g.col.device)
+    bf = ctypes.c_int64(0)
+    c = g.csr()
+    _check(L.bt_support_noalloc(ctypes.byref(c), _ptr(sup), ctypes.byref(bf), _stream(stream)))
     return sup, int(bf.value)
 
 

@@ -58,6 +58,12 @@ public:
     int64_t *host(int n);  // pinned, at least n int64; valid until a larger request
     void release();
     size_t bytes() const;
+    // Arena mode: buffers are carved from [base, base + cap), device memory
+    // the caller owns, and host scratch is `host` (n_host int64); nothing is
+    // allocated, and a request that does not fit throws BT_ENOMEM.  Every
+    // buffer is forgotten by release(), which a call in this mode makes
+    // first.
+    void use_arena(void *base, size_t cap, int64_t *host, int n_host);
 
     struct GraphEntry {
         std::vector<unsigned char> key;
@@ -76,6 +82,8 @@ private:
     std::vector<Buf> bufs_;
     int64_t *host_ = nullptr;
     int host_cap_ = 0;
+    char *arena_ = nullptr;
+    size_t arena_cap_ = 0, arena_top_ = 0;
 };
 
 void *device_alloc(size_t bytes);  // throws BT_ENOMEM with the size

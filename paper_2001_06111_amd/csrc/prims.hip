@@ -103,8 +103,38 @@ void device_free(void *p) {
 
 Workspace::~Workspace() { release(); }
 
+void Workspace::use_arena(void *base, size_t cap, int64_t *host, int n_host) {
+    release();
+    arena_ = static_cast<char *>(base);
+    arena_cap_ = cap;
+    arena_top_ = 0;
+    host_ = host;
+    host_cap_ = n_host;
+}
+
 void *Workspace::get(const char *name, size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
+    if (arena_) {
+        // Bump allocation; a name asked again for more memory gets a new
+        // region (the old one is reclaimed only by release()).
+        for (auto &b : bufs_)
+            if (b.name == name && b.cap >= bytes) return b.ptr;
+        if (arena_top_ + bytes > arena_cap_)
+            throw Error{BT_ENOMEM, "the call needs more than the " + std::to_string(arena_cap_) +
+                                       "-byte static scratch (" + std::string(name) + ")"};
+        Buf nb;
+        nb.name = name;
+        nb.ptr = arena_ + arena_top_;
+        nb.cap = bytes;
+        arena_top_ += bytes;
+        for (auto &b : bufs_)
+            if (b.name == name) {
+                b = nb;
+                return nb.ptr;
+            }
+        bufs_.push_back(nb);
+        return nb.ptr;
+    }
     for (auto &b : bufs_) {
         if (b.name == name) {
             if (b.cap < bytes) {
@@ -126,6 +156,11 @@ void *Workspace::get(const char *name, size_t bytes) {
 }
 
 void Workspace::release() {
+    if (arena_) {
+        bufs_.clear();
+        arena_top_ = 0;
+        return;
+    }
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
     for (auto &b : bufs_) device_free(b.ptr);
@@ -136,12 +171,17 @@ void Workspace::release() {
 }
 
 size_t Workspace::bytes() const {
+    if (arena_) return arena_top_;
     size_t t = 0;
     for (auto &b : bufs_) t += b.cap;
     return t;
 }
 
 int64_t *Workspace::host(int n) {
+    if (arena_) {
+        if (n > host_cap_) throw Error{BT_ENOMEM, "host scratch of the arena too small"};
+        return host_;
+    }
     if (n > host_cap_) {
         if (host_) (void)hipHostFree(host_);
         host_ = nullptr;
