@@ -160,6 +160,32 @@ void bt_index_free(bt_index *idx);
 bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
                        bt_stats *stats, hipStream_t stream);
 
+/*
+ * bt_decompose with a round-by-round trace, for inspecting the peel on small
+ * graphs (at most 65536 edges, else BT_EOVERFLOW): the rounds of the
+ * bulk-synchronous peel of Algorithm 5 (Section V-B) that remove edges,
+ * each with
+ *   round_level[k]             its level (the minimum support it peels at),
+ *   removed[k*m + e]           1 if edge e is removed in round k, else 0,
+ *   sup[k*m + e]               the support of e after round k (supports are
+ *                              lowered without the clamp at the level, so an
+ *                              edge removed earlier may read below it),
+ *   wedge_k[k*max_wedges + w]  the bloom number (live wedges) of the bloom
+ *                              holding wedge w after round k (its butterflies
+ *                              are k(k-1)/2),
+ * and the index it peeled through: wedge w is the twin pair
+ * (wedge_ea[w], wedge_eb[w]), as in bt_index_export.  All trace buffers are
+ * HOST memory of the sizes shown; *n_rounds and *n_wedges receive the counts
+ * (BT_EOVERFLOW if they exceed max_rounds or max_wedges).  phi_out is a
+ * device int64[m] as for bt_decompose.  The rounds run one at a time from
+ * the host, so this is slow; results equal bt_decompose.
+ */
+bt_status bt_decompose_trace(const bt_csr *g, int64_t *phi_out, int32_t max_rounds,
+                             int32_t *n_rounds, int32_t *round_level, int8_t *removed,
+                             int64_t *sup, int64_t max_wedges, int64_t *n_wedges,
+                             int32_t *wedge_ea, int32_t *wedge_eb, int32_t *wedge_k,
+                             hipStream_t stream);
+
 /* Peel variants, for measuring what batch bloom processing saves
  * (Section V-B and the evaluation of the batch optimisations). */
 typedef enum bt_peel_variant {

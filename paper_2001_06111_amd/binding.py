@@ -66,7 +66,8 @@ EXPORTED = ["bt_support", "bt_index_build", "bt_index_info_get", "bt_index_expor
             "bt_decompose_batch",
             "bt_bitruss_components", "bt_release_workspace", "bt_tune", "bt_tune_get",
             "bt_tune_set", "bt_tune_reset", "bt_tune_save", "bt_tune_load",
-            "bt_set_allocator", "bt_support_noalloc", "bt_last_error", "bt_version"]
+            "bt_set_allocator", "bt_support_noalloc", "bt_decompose_trace", "bt_last_error",
+            "bt_version"]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -94,6 +95,8 @@ def load():
                                            ctypes.POINTER(bt_stats), p]
         L.bt_decompose_pc.argtypes = [ctypes.POINTER(bt_csr), ctypes.c_double, p, p,
                                       ctypes.POINTER(bt_stats), p]
+        L.bt_decompose_trace.argtypes = [ctypes.POINTER(bt_csr), p, i32, ctypes.POINTER(i32),
+                                         p, p, p, i64, ctypes.POINTER(i64), p, p, p, p]
         L.bt_bitruss_components.argtypes = [ctypes.POINTER(bt_csr), p, i64, p,
                                             ctypes.POINTER(i64), p]
         L.bt_decompose_batch.argtypes = [ctypes.POINTER(bt_csr), i32, ctypes.POINTER(p),
@@ -110,7 +113,7 @@ def load():
         L.bt_set_allocator.restype = ctypes.c_int
         L.bt_last_error.restype = ctypes.c_char_p
         L.bt_version.restype = ctypes.c_char_p
-        for name in ("bt_support", "bt_support_noalloc", "bt_index_build", "bt_index_info_get", "bt_index_export",
+        for name in ("bt_support", "bt_support_noalloc", "bt_decompose_trace", "bt_index_build", "bt_index_info_get", "bt_index_export",
                      "bt_decompose", "bt_decompose_variant", "bt_decompose_pc",
                      "bt_decompose_batch",
                      "bt_bitruss_components", "bt_tune", "bt_tune_get", "bt_tune_set",
@@ -313,6 +316,33 @@ def bt_decompose_variant(g: DeviceGraph, variant: int, want_sup: bool = True,
                                   _ptr(phi), ctypes.byref(st) if stats else None,
                                   _stream(stream)))
     return sup, phi, (st.as_dict() if stats else None)
+
+
+def bt_decompose_trace(g: DeviceGraph, max_rounds: int = 256, max_wedges: int = 1 << 16,
+                       stream=None):
+    """Round-by-round trace of the peel (small graphs): dict with phi (device
+    tensor), level[k], removed[k, m] (bool), sup[k, m], wedge_ea, wedge_eb and
+    wedge_k[k, w] (numpy)."""
+    L = load()
+    m = g.m
+    phi = torch.empty(m, dtype=torch.int64, device=g.col.device)
+    lv = np.zeros(max_rounds, np.int32)
+    rm = np.zeros((max_rounds, m), np.int8)
+    sp = np.zeros((max_rounds, m), np.int64)
+    ea = np.zeros(max_wedges, np.int32)
+    eb = np.zeros(max_wedges, np.int32)
+    wk = np.zeros((max_rounds, max_wedges), np.int32)
+    nr, nw = ctypes.c_int32(0), ctypes.c_int64(0)
+
+    def p(a):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    c = g.csr()
+    _check(L.bt_decompose_trace(ctypes.byref(c), _ptr(phi), max_rounds, ctypes.byref(nr), p(lv),
+                                p(rm), p(sp), max_wedges, ctypes.byref(nw), p(ea), p(eb), p(wk),
+                                _stream(stream)))
+    k, w = nr.value, nw.value
+    return {"phi": phi, "level": lv[:k], "removed": rm[:k].astype(bool), "sup": sp[:k],
+            "wedge_ea": ea[:w], "wedge_eb": eb[:w], "wedge_k": wk[:k, :w]}
 
 
 def bt_decompose_pc(g: DeviceGraph, tau: float = 0.1, want_sup: bool = True, stats: bool = False,

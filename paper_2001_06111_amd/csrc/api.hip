@@ -301,6 +301,7 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
 }
 
 constexpr int64_t kMultiMaxEdges = int64_t(1) << 19;
+constexpr int64_t kTraceMaxEdges = int64_t(1) << 16;
 
 // A disjoint union of graphs (edge ranges [off[g], off[g+1])): one index
 // build for the union, then one peel in which every graph has its own level.
@@ -693,6 +694,59 @@ bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out, bt_s
         if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
         std::lock_guard<std::mutex> lk(lib().mu);
         decompose_impl(*g, sup_out, phi_out, stats, lib().ws, stream);
+    });
+}
+
+bt_status bt_decompose_trace(const bt_csr *g, int64_t *phi_out, int32_t max_rounds,
+                             int32_t *n_rounds, int32_t *round_level, int8_t *removed,
+                             int64_t *sup, int64_t max_wedges, int64_t *n_wedges,
+                             int32_t *wedge_ea, int32_t *wedge_eb, int32_t *wedge_k,
+                             hipStream_t stream) {
+    return guard([&] {
+        check_graph(g);
+        if (g->m > 0 && !phi_out) throw Error{BT_EINVAL, "phi_out is NULL"};
+        if (g->m > kTraceMaxEdges)
+            throw Error{BT_EOVERFLOW, "bt_decompose_trace takes at most 65536 edges"};
+        if (max_rounds < 0 || max_wedges < 0 || !n_rounds || !n_wedges ||
+            (max_rounds > 0 && (!round_level || !removed || !sup)) ||
+            (max_wedges > 0 && (!wedge_ea || !wedge_eb)) ||
+            (max_rounds > 0 && max_wedges > 0 && !wedge_k))
+            throw Error{BT_EINVAL, "invalid trace buffers"};
+        std::lock_guard<std::mutex> lk(lib().mu);
+        Workspace &ws = lib().ws;
+        const int64_t m = g->m;
+        RankCSR r;
+        IndexArrays ix;
+        build_all(*g, r, ix, false, nullptr, ws, stream, nullptr);
+        if (ix.n_w > max_wedges) throw Error{BT_EOVERFLOW, "more wedges than max_wedges"};
+        std::vector<PeelTraceRound> rounds;
+        const PeelTraceFn fn = [&](const PeelTraceRound &t) {
+            if ((int64_t)rounds.size() >= max_rounds)
+                throw Error{BT_EOVERFLOW, "more rounds than max_rounds"};
+            rounds.push_back(t);
+        };
+        PeelOptions o;
+        o.trace = &fn;
+        PeelCounters pc;
+        if (m > 0) peel(r, ix, nullptr, phi_out, pc, ws, stream, &o);
+        std::vector<int32_t> wbl((size_t)ix.n_w);
+        if (ix.n_w) {
+            BT_HIP(hipMemcpy(wedge_ea, ix.wea, sizeof(int32_t) * ix.n_w, hipMemcpyDeviceToHost));
+            BT_HIP(hipMemcpy(wedge_eb, ix.web, sizeof(int32_t) * ix.n_w, hipMemcpyDeviceToHost));
+            BT_HIP(hipMemcpy(wbl.data(), ix.wbl, sizeof(int32_t) * ix.n_w, hipMemcpyDeviceToHost));
+        }
+        for (size_t k = 0; k < rounds.size(); ++k) {
+            const PeelTraceRound &t = rounds[k];
+            round_level[k] = t.level;
+            int8_t *rm = removed + k * (size_t)m;
+            std::memset(rm, 0, (size_t)m);
+            for (int32_t e : t.removed) rm[e] = 1;
+            for (int64_t e = 0; e < m; ++e) sup[k * (size_t)m + e] = t.sup[(size_t)e];
+            for (int64_t w = 0; w < ix.n_w; ++w)
+                wedge_k[k * (size_t)max_wedges + w] = t.bloom_k[(size_t)wbl[(size_t)w]];
+        }
+        *n_rounds = (int32_t)rounds.size();
+        *n_wedges = ix.n_w;
     });
 }
 

@@ -865,9 +865,10 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     // BT_PEEL_VERBOSE=1 prints the time of the persistent launch.
     const bool verbose = std::getenv("BT_PEEL_VERBOSE") != nullptr;
     const char *mv = std::getenv("BT_PEEL_MODE");
-    const bool persistent = ws.coop && !(mv && std::strcmp(mv, "graph") == 0);
+    const PeelTraceFn *trace = opt && opt->trace && *opt->trace ? opt->trace : nullptr;
+    const bool persistent = ws.coop && !trace && !(mv && std::strcmp(mv, "graph") == 0);
     const char *gv = std::getenv("BT_PEEL_GRAPH");
-    const bool use_graph = !(gv && std::atoi(gv) == 0);
+    const bool use_graph = !trace && !(gv && std::atoi(gv) == 0);
     GridBar *bar = ws.get<GridBar>("peel_bar", 1);
     zero_bytes(bar, sizeof(GridBar), s);
     int pblocks = 0;
@@ -926,6 +927,7 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     int64_t n_all = m;
     int cur = -1;  // -1: all edges, in id order
     int chunk = 4;
+    int tp = 0;  // trace mode: parity of the next round
     bool need_refill = true;
     for (int64_t guard = 0;; ++guard) {
         if (need_refill) {
@@ -985,6 +987,43 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
             st.thresh = (int32_t)thresh;
             BT_HIP(hipMemcpyAsync(P.ctl, &st, sizeof st, hipMemcpyHostToDevice, s));
             need_refill = false;
+        }
+        if (trace) {
+            // One round at a time: the frontier it removes is read before it
+            // runs, supports and bloom numbers after.
+            BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+            BT_HIP(hipStreamSynchronize(s));
+            const int64_t nf = hc->stall ? 0 : (int64_t)hc->nf[tp].v;
+            std::vector<FrontItem> items((size_t)nf);
+            if (nf)
+                BT_HIP(hipMemcpy(items.data(), P.front[tp], sizeof(FrontItem) * nf,
+                                 hipMemcpyDeviceToHost));
+            launch_round(P, tp, s);
+            BT_CHECK_LAUNCH();
+            BT_HIP(hipMemcpyAsync(hc, P.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+            BT_HIP(hipStreamSynchronize(s));
+            if (hc->stall) {
+                need_refill = true;
+                tp = 0;
+                continue;
+            }
+            if (hc->mode[tp] == kNormal) {
+                PeelTraceRound tr;
+                tr.level = hc->level[tp];
+                for (const FrontItem &it : items)
+                    if (tr.removed.empty() || tr.removed.back() != it.e) tr.removed.push_back(it.e);
+                tr.sup.resize((size_t)m);
+                tr.bloom_k.resize((size_t)ix.n_b);
+                BT_HIP(hipMemcpy(tr.sup.data(), P.sup, sizeof(int32_t) * m,
+                                 hipMemcpyDeviceToHost));
+                if (ix.n_b)
+                    BT_HIP(hipMemcpy(tr.bloom_k.data(), ix.bk, sizeof(int32_t) * ix.n_b,
+                                     hipMemcpyDeviceToHost));
+                (*trace)(tr);
+            }
+            tp ^= 1;
+            if (guard > 4 * m + 64) throw Error{BT_EDEVICE, "peel made no progress"};
+            continue;
         }
         BT_HIP(hipEventRecord(ev0, s));
         if (use_graph) {

@@ -139,13 +139,25 @@ struct PeelCounters {
     double kernel_ms = 0;  // HIP-event time of the peel kernel launches
     int64_t launches = 0;
 };
+// One round of a traced peel (only rounds that remove edges): its level,
+// the edges it removed, and every support and bloom number after it.
+struct PeelTraceRound {
+    int32_t level = 0;
+    std::vector<int32_t> removed;
+    std::vector<int32_t> sup;
+    std::vector<int32_t> bloom_k;
+};
+using PeelTraceFn = std::function<void(const PeelTraceRound &)>;
 // Progressive mode (Section V-C): `fixed` (per edge, nullable) marks edges
 // whose bitruss numbers an earlier pass fixed; the index must carry their
 // marks (mark_fixed).  The first level is at least `min_level`.
+// `trace` (nullable): run the rounds one at a time from the host and report
+// each (small graphs; for inspection and tests).
 struct PeelOptions {
     const int32_t *fixed = nullptr;
     int32_t min_level = 0;
     bool unit_updates = false;  // ablation: no batch bloom processing
+    const PeelTraceFn *trace = nullptr;
 };
 void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
           PeelCounters &pc, Workspace &ws, hipStream_t s, const PeelOptions *opt = nullptr);

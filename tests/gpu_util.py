@@ -49,7 +49,25 @@ def canonical_gpu_index(g, ex):
     return out
 
 
+def check_links(g, ex):
+    """Edge-to-wedge links (Section IV, Definitions 8-9; the transpose built by
+    the last step of Algorithm 3): edge e links exactly the wedges holding it,
+    once each, so the links of all edges are every wedge twice."""
+    m = g.m
+    ea, eb = ex["wedge_ea"].astype(np.int64), ex["wedge_eb"].astype(np.int64)
+    nw = ea.shape[0]
+    off, link = ex["link_off"], ex["link"]
+    assert off[0] == 0 and off[m] == 2 * nw and np.all(np.diff(off) >= 0)
+    want = [[] for _ in range(m)]
+    for w in range(nw):
+        want[ea[w]].append(w)
+        want[eb[w]].append(w)
+    for e in range(m):
+        assert sorted(link[off[e]:off[e + 1]].tolist()) == sorted(want[e]), e
+
+
 def check_index(g, ex):
     want = index_def.blooms(g.n_upper, g.n_lower, g.row_ptr, g.col)
     got = canonical_gpu_index(g, ex)
     assert got == want
+    check_links(g, ex)

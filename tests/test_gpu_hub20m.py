@@ -1,8 +1,10 @@
-"""Full-size checks on the 20M-edge hub-skewed Chung-Lu workload.
+"""Checks on the 20M-edge hub-skewed Chung-Lu workload.
 
-The oracle's peel is far too slow at this size, so the bitruss numbers are
-checked through properties that hold at any size, each computed by the
-oracle from the GPU's answer:
+Bitruss numbers of vertex-sampled induced subgraphs are compared bit for bit
+with the oracle's digests, by the plain peel and by BiT-PC; on the full
+graph the two must agree, match the oracle's digest where it has been
+written (its peel takes hours here), and satisfy properties that hold at
+any size, each computed by the oracle from the GPU's answer:
   * supports: SHA-256 of the oracle's full support vector and the butterfly
     total (tests/golden/digests.json, written by make_digests.py);
   * 0 <= phi_e <= support_e (Lemma 10's bound), and max phi <= k_max, the
@@ -45,19 +47,67 @@ def sub_support(g, ids):
 
 
 @pytest.fixture(scope="module")
-def c2():
-    # BiT-PC (the paper's method for hub-heavy graphs; the plain peel gives the
-    # same numbers here in about twice the time).
+def hub():
     g = synth.plain_hub_20m()
-    print(f"[hub20m] generated m={g.m}; decomposing on the GPU (BiT-PC)", flush=True)
-    sup, phi, st = binding.bt_decompose_pc(binding.DeviceGraph.upload(g), tau=0.05, stats=True)
+    print(f"[hub20m] generated m={g.m}", flush=True)
+    return g
+
+
+@pytest.fixture(scope="module")
+def c2(hub):
+    """The plain peel (Algorithm 5) and BiT-PC (Algorithm 7) on the full graph."""
+    g = hub
+    dg = binding.DeviceGraph.upload(g)
+    print("[hub20m] decomposing on the GPU (plain peel)", flush=True)
+    sup, phi, st = binding.bt_decompose(dg, stats=True)
     torch.cuda.synchronize()
-    print(f"[hub20m] decomposed: rounds {st['rounds']}, max phi {st['max_phi']}", flush=True)
-    return g, sup.cpu().numpy(), phi.cpu().numpy(), st
+    print(f"[hub20m] plain: rounds {st['rounds']}, max phi {st['max_phi']}; now BiT-PC", flush=True)
+    _, phi_pc, st_pc = binding.bt_decompose_pc(dg, tau=0.05, want_sup=False, stats=True)
+    torch.cuda.synchronize()
+    print(f"[hub20m] BiT-PC: passes {st_pc['passes']}", flush=True)
+    return g, sup.cpu().numpy(), phi.cpu().numpy(), st, phi_pc.cpu().numpy()
+
+
+def test_hub20m_plain_equals_pc(c2):
+    g, sup, phi, st, phi_pc = c2
+    assert np.array_equal(phi, phi_pc)
+
+
+def test_hub20m_phi_digest(c2):
+    """Bit-exact against the oracle's full bitruss numbers, once that run
+    (hours on a CPU) has written its digest."""
+    g, sup, phi, st, phi_pc = c2
+    want = GOLD[g.name].get("phi_sha256")
+    if want is None:
+        pytest.skip("no oracle phi digest for the full 20M-edge graph in digests.json")
+    assert sha(phi) == want and sha(phi_pc) == want
+
+
+SAMPLES = sorted(k for k, v in GOLD.items()
+                 if isinstance(v, dict) and v.get("sample", {}).get("of") == "chunglu-100kx2M-m20M-hub")
+
+
+@pytest.mark.parametrize("key", SAMPLES)
+def test_hub20m_vertex_sample_digests(hub, key):
+    """Vertex-sampled induced subgraphs of the hub graph (the paper's
+    scalability sampling), bit-exact against the oracle by the plain peel
+    and by BiT-PC."""
+    want = GOLD[key]
+    smp = synth.vertex_sample(hub, want["sample"]["fraction"], want["sample"]["seed"])
+    assert smp.name == key and smp.m == want["m"]
+    dg = binding.DeviceGraph.upload(smp)
+    sup, phi, st = binding.bt_decompose(dg, stats=True)
+    _, phi_pc, _ = binding.bt_decompose_pc(dg, tau=0.05, want_sup=False)
+    torch.cuda.synchronize()
+    print(f"[hub20m] {key}: rounds {st['rounds']}", flush=True)
+    assert st["butterflies"] == want["butterflies"]
+    assert sha(sup.cpu().numpy()) == want["sup_sha256"]
+    assert sha(phi.cpu().numpy()) == want["phi_sha256"]
+    assert sha(phi_pc.cpu().numpy()) == want["phi_sha256"]
 
 
 def test_hub20m_supports(c2):
-    g, sup, phi, st = c2
+    g, sup, phi, st, _ = c2
     want = GOLD[g.name]
     assert want["generator_version"] == synth.GENERATOR_VERSION
     assert st["butterflies"] == want["butterflies"]
@@ -65,7 +115,7 @@ def test_hub20m_supports(c2):
 
 
 def test_hub20m_phi_bounds(c2):
-    g, sup, phi, st = c2
+    g, sup, phi, st, _ = c2
     assert np.all(phi >= 0) and np.all(phi <= sup)
     s = np.sort(sup)[::-1]
     kmax = int(np.max(np.minimum(s, np.arange(1, len(s) + 1))))
@@ -73,7 +123,7 @@ def test_hub20m_phi_bounds(c2):
 
 
 def test_hub20m_soundness(c2):
-    g, sup, phi, st = c2
+    g, sup, phi, st, _ = c2
     pos = np.sort(phi[phi > 0])
     ks = sorted({1, int(pos[len(pos) // 2]), int(pos[int(len(pos) * 0.9)]),
                  int(pos[int(len(pos) * 0.99)]), int(phi.max())})
@@ -85,7 +135,7 @@ def test_hub20m_soundness(c2):
 
 
 def test_hub20m_maximality_top_levels(c2):
-    g, sup, phi, st = c2
+    g, sup, phi, st, _ = c2
     levels = np.unique(phi)[::-1][:3]
     for k in levels:
         k = int(k)
