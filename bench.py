@@ -197,7 +197,7 @@ def plain_loop(dgs, ref_phis, budget_s):
     return time.perf_counter() - t0, done, same
 
 
-def single(name, g, reps, warmup, golden, variant=None, tau=None):
+def single(name, g, reps, warmup, golden, variant=None, tau=None, traffic=None):
     import torch
     from paper_2001_06111_amd import binding
     dg = binding.DeviceGraph.upload(g, "cuda:0")
@@ -234,7 +234,8 @@ def single(name, g, reps, warmup, golden, variant=None, tau=None):
            "counters": {k: st[k] for k in ("butterflies", "wedges_po", "blooms", "bloom_wedges",
                                            "levels", "rounds", "max_phi", "support_updates",
                                            "wedge_visits", "passes")}}
-    out["roofline"] = roofline("k_peel_persistent", st, None)
+    out["roofline"] = roofline("k_peel_persistent", st,
+                               traffic * max(1, st["peel_launches"]) if traffic else None)
     del dg, phi
     torch.cuda.empty_cache()
     return out
@@ -345,13 +346,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--budget", type=float, default=450.0,
+    ap.add_argument("--budget", type=float, default=480.0,
                     help="wall seconds for the whole run; extras that would not fit are skipped")
     ap.add_argument("--single", default="c0,c1,c2",
                     help="single-graph lines: any of c0,c1,c2 (empty: none)")
     ap.add_argument("--c2-plain", type=int, default=1,
                     help="also time the 20M-edge hub graph by the plain peel (besides BiT-PC)")
-    ap.add_argument("--serve", type=float, default=2.0,
+    ap.add_argument("--serve", type=float, default=1.0,
                     help="seconds of Poisson arrivals for served vs plain FIFO (0: skip)")
     ap.add_argument("--slots", type=int, default=2, help="serving engine slots")
     ap.add_argument("--plain", type=int, default=1, help="plain per-graph loop (0: skip)")
@@ -460,7 +461,10 @@ def main():
         if key in args.single and key in inputs:
             if left(args.budget) > costs[key][1] + 10:
                 log(f"single {key}")
-                singles[key] = single(key, inputs[key], 5 if key == "c1" else 20, 1, golden)
+                tr = measured_traffic("peel_chunglu5m_traffic.md", ("peel.hip", "peel_common.h")) \
+                    if key == "c1" else None
+                singles[key] = single(key, inputs[key], 5 if key == "c1" else 20, 1, golden,
+                                      traffic=tr)
                 if key == "c1":
                     _, _, st_e = binding.bt_decompose_variant(
                         binding.DeviceGraph.upload(inputs["c1"], "cuda:0"),

@@ -149,3 +149,35 @@ def test_engine_two_slots_stay_within_budget():
     assert mem["peak_committed"] <= budget and mem["peak_held"] <= budget, mem
     for i in range(len(gs)):
         assert torch.equal(res[i][2], res0[i][2])
+
+
+def test_engine_request_mix_alone_equals_mix():
+    """The serving mix (pool graphs with 2M-edge request graphs, arriving
+    while others run, two slots): every result equals the plain
+    single-graph decomposition of the same request, and request graph 0
+    equals the oracle's digest."""
+    import hashlib
+    import json
+    import os
+    import time
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "digests.json")))
+    small = [synth.batch_graph(i) for i in range(30)]
+    big = [synth.big_serving_graph(0), synth.big_serving_graph(1)]
+    gs = small[:10] + big[:1] + small[10:20] + big[1:] + small[20:]
+    dgs = [upload(g) for g in gs]
+    eng = binding.BtEngine(slots=2)
+    for i, d in enumerate(dgs):
+        eng.bt_engine_submit(d, i)
+        time.sleep(0.005)
+    eng.bt_engine_drain()
+    done = dict(eng.bt_engine_poll())
+    eng.bt_engine_destroy()
+    assert sorted(done) == list(range(len(gs)))
+    for i, d in enumerate(dgs):
+        assert done[i] == binding.BT_OK
+        _, phi, _ = binding.bt_decompose(d, want_sup=False)
+        assert torch.equal(eng.results[i][2], phi), gs[i].name
+    i0 = gs.index(big[0])
+    want = gold["big:1"]["per_graph"][0]["phi_sha256"]
+    got = hashlib.sha256(eng.results[i0][2].cpu().numpy().astype("<i8").tobytes()).hexdigest()
+    assert got == want
