@@ -23,8 +23,9 @@
 //            batch's index is built, the exact peel state it still needs.
 // A slot admits a batch of estimate E only if sum over slots of held + res,
 // with its own res = E, stays within the budget; if its own cached
-// workspace is what stands in the way it frees it first, and idle slots
-// whose cached workspaces block an admission are asked to free theirs.
+// workspace is what stands in the way it frees it first (the bytes count
+// until they are freed) and decides again, and idle slots whose cached
+// workspaces block an admission are asked to free theirs.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -154,7 +155,6 @@ void bt_engine::worker_loop(int slot) {
     while (true) {
         std::vector<Request> batch;
         int64_t bytes = 0, held0 = 0;
-        bool free_first = false;
         {
             std::unique_lock<std::mutex> lk(mu);
             Slot &me = slots[(size_t)slot];
@@ -193,22 +193,32 @@ void bt_engine::worker_loop(int slot) {
                 }
                 continue;
             }
-            // Admit requests of the chosen class in arrival order while the
-            // budget allows (this slot's own cache may be freed to make room).
+            // If this slot's own cached workspace is what keeps the oldest
+            // request of the class out, free it first (its bytes stay
+            // counted until it is freed), then decide again.
             const int64_t others = committed_except(slot);
+            if (me.held > 0 && others + me.held + first_of(cls)->bytes > budget) {
+                lk.unlock();
+                ws.release();
+                lk.lock();
+                me.held = 0;
+                note_peaks();
+                cv_work.notify_all();
+                continue;
+            }
+            // Admit requests of the chosen class in arrival order while the
+            // budget, this slot's cache included, allows.
             const int32_t cap = cls == 2 ? std::min(max_batch, kLargePerBatch) : max_batch;
             for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < cap;) {
                 if (size_class_of(it->g.m) != cls) {
                     ++it;
                     continue;
                 }
-                if (others + bytes + it->bytes > budget) break;
+                if (others + me.held + bytes + it->bytes > budget) break;
                 bytes += it->bytes;
                 batch.push_back(*it);
                 it = queue.erase(it);
             }
-            free_first = others + me.held + bytes > budget;
-            if (free_first) me.held = 0;  // freed below, before any allocation
             held0 = me.held;
             me.res = bytes;
             me.busy = true;
@@ -217,7 +227,6 @@ void bt_engine::worker_loop(int slot) {
             admitted += (int64_t)batch.size();
             note_peaks();
         }
-        if (free_first) ws.release();
         std::vector<bt_csr> gs;
         std::vector<int64_t *> sups, phis;
         for (auto &r : batch) {
