@@ -97,6 +97,9 @@ typedef struct bt_stats {
     int64_t wedge_visits;     /* live wedges of touched blooms visited by batch
                                  bloom processing, summed over rounds: each such
                                  visit lowers the wedge's two edges once */
+    int64_t peel_yields;      /* peel launches that ended early to give the
+                                 device to a peel of a much smaller batch
+                                 waiting in another thread, then resumed */
 } bt_stats;
 
 /* Opaque device-resident BE-Index. */
@@ -331,7 +334,11 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   the engine (0: half of the free memory); at most `max_batch` requests
  *   per batch (0: 1024).  The peel of a batch holds most of the GPU, so the
  *   peels of different slots take turns; a second slot counts and builds
- *   the index of the next batch while one slot's batch peels.
+ *   the index of the next batch while one slot's batch peels, and when that
+ *   batch has under 1/8 of the running peel's edges, the running peel (if
+ *   it is the single-graph persistent peel of a large batch) ends its
+ *   launch at its next rebuild of the active set, lets the smaller batch
+ *   peel, and resumes where it stopped.
  *   Memory: the budget covers every slot's cached workspace plus what its
  *   running batch may still allocate (the submit-time estimate, replaced by
  *   the exact peel state once the batch's index is built); a slot frees its
@@ -369,9 +376,11 @@ bt_status bt_engine_submit(bt_engine *engine, const bt_csr *g, int64_t *sup_out,
 bt_status bt_engine_poll(bt_engine *engine, uint64_t *ids, int32_t *status, int32_t cap,
                          int32_t *n_done);
 bt_status bt_engine_drain(bt_engine *engine);
-/* Batches run, requests admitted and requests waiting (host pointers, nullable). */
+/* Batches run, requests admitted, requests waiting, and peel launches that
+ * gave the device to a much smaller batch of another slot (host pointers,
+ * nullable). */
 bt_status bt_engine_stats(bt_engine *engine, int64_t *batches, int64_t *admitted,
-                          int64_t *queued);
+                          int64_t *queued, int64_t *peel_yields);
 /* Host pointers, nullable. */
 bt_status bt_engine_memory(bt_engine *engine, int64_t *budget, int64_t *held,
                            int64_t *peak_held, int64_t *peak_committed);

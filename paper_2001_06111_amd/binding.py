@@ -40,7 +40,8 @@ class bt_stats(ctypes.Structure):
         (n, ctypes.c_float) for n in ("ms_prepare", "ms_count", "ms_link", "ms_peel",
                                       "ms_peel_kernel")] + [
         ("peel_launches", ctypes.c_int32), ("passes", ctypes.c_int32),
-        ("support_updates_unbatched", ctypes.c_int64), ("wedge_visits", ctypes.c_int64)]
+        ("support_updates_unbatched", ctypes.c_int64), ("wedge_visits", ctypes.c_int64),
+        ("peel_yields", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -459,8 +460,7 @@ def _engine_lib():
         L.bt_engine_poll.argtypes = [p, ctypes.POINTER(u64), ctypes.POINTER(i32), i32,
                                      ctypes.POINTER(i32)]
         L.bt_engine_drain.argtypes = [p]
-        L.bt_engine_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                      ctypes.POINTER(i64)]
+        L.bt_engine_stats.argtypes = [p] + [ctypes.POINTER(i64)] * 4
         L.bt_engine_memory.argtypes = [p] + [ctypes.POINTER(i64)] * 4
         L.bt_engine_destroy.argtypes = [p]
         L.bt_engine_destroy.restype = None
@@ -518,10 +518,11 @@ class BtEngine:
         _check(_engine_lib().bt_engine_drain(self._h))
 
     def bt_engine_stats(self):
-        b, a, q = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        b, a, q, y = (ctypes.c_int64(0) for _ in range(4))
         _check(_engine_lib().bt_engine_stats(self._h, ctypes.byref(b), ctypes.byref(a),
-                                             ctypes.byref(q)))
-        return {"batches": b.value, "admitted": a.value, "queued": q.value}
+                                             ctypes.byref(q), ctypes.byref(y)))
+        return {"batches": b.value, "admitted": a.value, "queued": q.value,
+                "peel_yields": y.value}
 
     def bt_engine_memory(self):
         v = [ctypes.c_int64(0) for _ in range(4)]

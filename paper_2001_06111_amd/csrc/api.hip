@@ -157,6 +157,7 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->passes = 1;
     stats->support_updates_unbatched = pc.updates_unbatched;
     stats->wedge_visits = pc.touched;
+    stats->peel_yields = pc.yields;
 }
 
 }  // namespace
@@ -264,6 +265,7 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
             tot.updates += pc.updates;
             tot.bloom_visits += pc.bloom_visits;
             tot.touched += pc.touched;
+            tot.yields += pc.yields;
             tot.kernel_ms += pc.kernel_ms;
             tot.launches += pc.launches;
             blooms += ix.n_b;
@@ -297,6 +299,7 @@ void decompose_pc_impl(const bt_csr &g, double tau, int64_t *sup_out, int64_t *p
         stats->peel_launches = (int32_t)tot.launches;
         stats->passes = passes;
         stats->wedge_visits = tot.touched;
+        stats->peel_yields = tot.yields;
     }
 }
 
@@ -417,6 +420,7 @@ void add_stats(bt_stats &t, const bt_stats &s) {
     t.passes = std::max(t.passes, s.passes);
     t.support_updates_unbatched += s.support_updates_unbatched;
     t.wedge_visits += s.wedge_visits;
+    t.peel_yields += s.peel_yields;
 }
 
 // Graphs [a, b) as one union; splits the range if the union is too large.

@@ -51,6 +51,15 @@ inline int bits_for(uint64_t v) {  // bits needed to store values in [0, v]
 class Workspace {
 public:
     ~Workspace();
+    // Binds the workspace to the one stream that uses its buffers: they are
+    // then allocated and freed in stream order (hipMallocAsync and
+    // hipFreeAsync on s), since hipFree and hipHostFree wait for every
+    // stream of the device, including a long peel of another caller.  Host
+    // scratch is then freed only by the destructor.  Call before any get().
+    void bind_stream(hipStream_t s) { stream_ = s; }
+    // Frees everything, host scratch included, and unbinds; call before the
+    // bound stream is destroyed.
+    void close();
     void *get(const char *name, size_t bytes);
     template <typename T> T *get(const char *name, int64_t count) {
         return static_cast<T *>(get(name, (size_t)(count > 0 ? count : 1) * sizeof(T)));
@@ -82,11 +91,16 @@ private:
     std::vector<Buf> bufs_;
     int64_t *host_ = nullptr;
     int host_cap_ = 0;
+    hipStream_t stream_ = nullptr;
+    std::vector<int64_t *> old_host_;  // outgrown host scratch of a bound workspace
     char *arena_ = nullptr;
     size_t arena_cap_ = 0, arena_top_ = 0;
 };
 
-void *device_alloc(size_t bytes);  // throws BT_ENOMEM with the size
+// Throws BT_ENOMEM with the size.  With a stream, the block is allocated
+// (and later freed) in that stream's order; a hook's block is then handed
+// back after that stream alone has drained, not the whole device.
+void *device_alloc(size_t bytes, hipStream_t stream = nullptr);
 void device_free(void *p);
 void set_allocator(bt_alloc_fn a, bt_free_fn f, void *ctx);
 

@@ -28,6 +28,7 @@
 // workspaces block an admission are asked to free theirs.
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -100,6 +101,16 @@ struct bt_engine {
     hipStream_t est_stream = nullptr;
     int device = 0;
     int64_t batches = 0, admitted = 0;
+    int64_t peel_yields = 0;  // peel launches of large batches that gave way
+    // BT_ENGINE_VERBOSE=1: one line per batch admitted and done, with times
+    // since the engine was created.
+    bool verbose = std::getenv("BT_ENGINE_VERBOSE") != nullptr;
+    std::chrono::steady_clock::time_point t_created = std::chrono::steady_clock::now();
+    double ms_since_created() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                         t_created)
+            .count();
+    }
     int64_t peak_committed = 0;  // largest sum of held + res seen
     int64_t peak_held = 0;       // largest sum of held seen
 
@@ -152,6 +163,7 @@ void bt_engine::worker_loop(int slot) {
     hipStream_t s = nullptr;
     (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     Workspace ws;  // cooperative peels of different slots take turns (see peel.hip)
+    ws.bind_stream(s);
     while (true) {
         std::vector<Request> batch;
         int64_t bytes = 0, held0 = 0;
@@ -226,6 +238,13 @@ void bt_engine::worker_loop(int slot) {
             batches += 1;
             admitted += (int64_t)batch.size();
             note_peaks();
+            if (verbose) {
+                int64_t edges = 0;
+                for (auto &r : batch) edges += r.g.m;
+                std::fprintf(stderr, "[engine] %.1f ms slot %d admits %zu requests of class %d, %lld edges (queue %zu)\n",
+                             ms_since_created(), slot, batch.size(), cls, (long long)edges,
+                             queue.size());
+            }
         }
         std::vector<bt_csr> gs;
         std::vector<int64_t *> sups, phis;
@@ -247,8 +266,9 @@ void bt_engine::worker_loop(int slot) {
             cv_work.notify_all();
         };
         std::vector<Done> out;
+        bt_stats bst{};
         try {
-            decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), nullptr,
+            decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), &bst,
                                  ws, s, &on_sized);
             for (auto &r : batch) out.push_back(Done{r.id, BT_OK});
         } catch (const Error &) {
@@ -275,13 +295,17 @@ void bt_engine::worker_loop(int slot) {
             me.res = 0;
             me.busy = false;
             note_peaks();
+            peel_yields += bst.peel_yields;
+            if (verbose)
+                std::fprintf(stderr, "[engine] %.1f ms slot %d done (%zu requests, %lld peel yields)\n",
+                             ms_since_created(), slot, batch.size(), (long long)bst.peel_yields);
             running -= (int64_t)batch.size();
             for (auto &d : out) done.push_back(d);
         }
         cv_work.notify_all();
         cv_idle.notify_all();
     }
-    ws.release();
+    ws.close();
     if (s) (void)hipStreamDestroy(s);
 }
 
@@ -306,6 +330,7 @@ bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
         E->max_batch = max_batch > 0 ? max_batch : 1024;
         BT_HIP(hipStreamCreateWithFlags(&E->est_stream, hipStreamNonBlocking));
         E->est_ws.coop = false;
+        E->est_ws.bind_stream(E->est_stream);
         const int n = slots > 0 ? slots : kDefaultSlots;
         E->slots.resize((size_t)n);
         for (int i = 0; i < n; ++i) E->workers.emplace_back(&bt_engine::worker_loop, E, i);
@@ -379,7 +404,8 @@ bt_status bt_engine_drain(bt_engine *E) {
     return BT_OK;
 }
 
-bt_status bt_engine_stats(bt_engine *E, int64_t *batches, int64_t *admitted, int64_t *queued) {
+bt_status bt_engine_stats(bt_engine *E, int64_t *batches, int64_t *admitted, int64_t *queued,
+                          int64_t *peel_yields) {
     if (!E) {
         set_error("engine is NULL");
         return BT_EINVAL;
@@ -388,6 +414,7 @@ bt_status bt_engine_stats(bt_engine *E, int64_t *batches, int64_t *admitted, int
     if (batches) *batches = E->batches;
     if (admitted) *admitted = E->admitted;
     if (queued) *queued = (int64_t)E->queue.size();
+    if (peel_yields) *peel_yields = E->peel_yields;
     return BT_OK;
 }
 
@@ -416,7 +443,7 @@ void bt_engine_destroy(bt_engine *E) {
     }
     E->cv_work.notify_all();
     for (auto &t : E->workers) t.join();
-    E->est_ws.release();
+    E->est_ws.close();
     if (E->est_stream) (void)hipStreamDestroy(E->est_stream);
     delete E;
 }

@@ -46,13 +46,106 @@
 // An ablation mode (`unit`) drops batch bloom processing: each survivor
 // takes C[B] decrements of one instead of one decrement of C[B].
 // Batches of graphs peel in k_peel_multi, each graph at its own level.
+#include <condition_variable>
+#include <map>
+#include <memory>
+
 #include "peel_common.h"
 
 namespace bt {
 
-std::mutex &coop_mutex() {
-    static std::mutex *m = new std::mutex();  // never destroyed: outlives static teardown
-    return *m;
+namespace {
+
+// Turns of the cooperative peels: tickets in asking order, the waiting
+// tickets with their weights (edges), and the yield word the holder's
+// kernel reads.  Never destroyed: it outlives static teardown.
+struct Gate {
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t next = 0;
+    bool busy = false;
+    int64_t holder_weight = 0;
+    std::map<uint64_t, int64_t> waiting;
+    int32_t *word = nullptr;  // pinned, coherent: [0] yield request, [1] always 1
+    int32_t *dword = nullptr;  // its device address
+};
+
+constexpr int64_t kYieldRatio = 8;
+
+Gate &gate() {
+    static Gate *g = new Gate();
+    return *g;
+}
+
+// Under g.mu: raise the yield word when some waiter is much lighter than
+// the holder, clear it otherwise.
+void update_yield(Gate &g) {
+    bool ask = false;
+    if (g.busy)
+        for (const auto &w : g.waiting)
+            if (w.second * kYieldRatio < g.holder_weight) {
+                ask = true;
+                break;
+            }
+    if (!g.word) return;
+    static const bool verbose = std::getenv("BT_PEEL_VERBOSE") != nullptr;
+    if (verbose && (g.word[0] != 0) != ask)
+        std::fprintf(stderr, "[peel] yield word %d (holder %lld edges, %zu waiting)\n", ask ? 1 : 0,
+                     (long long)g.holder_weight, g.waiting.size());
+    __atomic_store_n(&g.word[0], ask ? 1 : 0, __ATOMIC_RELEASE);
+}
+
+// Under g.mu, with `ticket` in g.waiting: waits for it to be the oldest
+// waiter while the device is free, then takes the turn.
+void take_turn(Gate &g, std::unique_lock<std::mutex> &lk, uint64_t ticket, int64_t weight) {
+    update_yield(g);
+    g.cv.wait(lk, [&] { return !g.busy && g.waiting.begin()->first == ticket; });
+    g.waiting.erase(ticket);
+    g.busy = true;
+    g.holder_weight = weight;
+    update_yield(g);
+}
+
+}  // namespace
+
+CoopTurn::CoopTurn(int64_t weight) : weight_(weight) {
+    Gate &g = gate();
+    std::unique_lock<std::mutex> lk(g.mu);
+    if (!g.word) {
+        void *h = nullptr, *d = nullptr;
+        BT_HIP(hipHostMalloc(&h, 2 * sizeof(int32_t),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+        BT_HIP(hipHostGetDevicePointer(&d, h, 0));
+        g.word = static_cast<int32_t *>(h);
+        g.word[0] = 0;
+        g.word[1] = 1;
+        g.dword = static_cast<int32_t *>(d);
+    }
+    ticket_ = g.next++;
+    g.waiting[ticket_] = weight_;
+    take_turn(g, lk, ticket_, weight_);
+}
+
+CoopTurn::~CoopTurn() {
+    Gate &g = gate();
+    std::lock_guard<std::mutex> lk(g.mu);
+    g.busy = false;
+    g.holder_weight = 0;
+    update_yield(g);
+    g.cv.notify_all();
+}
+
+const int32_t *CoopTurn::yield_word(bool force) const { return gate().dword + (force ? 1 : 0); }
+
+void CoopTurn::requeue() {
+    Gate &g = gate();
+    std::unique_lock<std::mutex> lk(g.mu);
+    g.busy = false;
+    g.holder_weight = 0;
+    ticket_ = g.next++;
+    g.waiting[ticket_] = weight_;
+    g.cv.notify_all();
+    take_turn(g, lk, ticket_, weight_);
 }
 
 namespace {
@@ -458,9 +551,16 @@ struct RefillState {
     int32_t cur;       // list holding the remaining edges; -1: all edges, in id order
     int64_t n_all;     // its length
     int32_t done;      // set when no edge remains
-    int32_t pad;
+    int32_t yield_req;  // the yield word as the lead last read it
+    int32_t yielded;    // set when the launch ended early to give way
+    int32_t resume_p;   // -1: start with a rebuild; else decide round parity resume_p
+    u64 yield_src;      // address of the host-written yield word (0: none)
     u64 hist[33];
 };
+
+// Every kYieldEvery rounds the lead reads the host's yield word (one read
+// over the host link, off the rounds' critical path but for one barrier).
+constexpr int64_t kYieldEvery = 32;
 
 struct RefillArgs {
     RefillState *rs;
@@ -632,8 +732,10 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
                                                              int64_t max_rounds, int prof,
                                                              RefillArgs RA) {
     PeelCtl *C = P.ctl;
+    RefillState *RS = RA.rs;
     __shared__ Round sR;
-    __shared__ int s_ok, s_fail;
+    __shared__ int s_ok, s_fail, s_y, s_p;
+    __shared__ const int32_t *s_ys;
     u64 gen_local = 0;  // barriers passed (the host clears the barrier per launch)
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     // Wave ids run across blocks first: a small round spreads its work items
@@ -641,7 +743,6 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
     // pipelines with scattered accesses.
     const int64_t wid = (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
     const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
-    int p = 0;
     // The lead's clocks and counters live in LDS, not in every lane's
     // registers (which would push the kernel past 128 VGPRs into spills).
     __shared__ u64 t[5], acc[6];
@@ -651,18 +752,28 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         L.load(C);
         for (int k = 0; k < 6; ++k) acc[k] = 0;
     }
-    if (threadIdx.x == 0) s_fail = 0;
+    if (threadIdx.x == 0) {
+        s_fail = 0;
+        s_y = 0;
+        s_p = ld(&RS->resume_p);
+        s_ys = reinterpret_cast<const int32_t *>(ld(&RS->yield_src));
+    }
     __syncthreads();
-    int64_t r = 0;
+    // A launch resumes where the previous one yielded (deciding the round
+    // of parity s_p), or starts with a rebuild of the active set.
+    int p = s_p;
+    int64_t r = 0;  // rounds of this launch
     while (r < max_rounds) {
     // The active set is (re)built here whenever it runs dry; the peel ends
     // when no edge remains.
-    int ok = 1;
-    if (grid_refill(P, RA, B, gen_local, lead, ok) == 0) {
-        if (!ok && threadIdx.x == 0) s_fail = 1;
-        break;
+    if (p < 0) {
+        int ok = 1;
+        if (grid_refill(P, RA, B, gen_local, lead, ok) == 0) {
+            if (!ok && threadIdx.x == 0) s_fail = 1;
+            break;
+        }
+        p = 0;
     }
-    p = 0;
     if (threadIdx.x == 0) s_ok = decide_round(C, p, lead, sR, L, P.prof);
     __syncthreads();
     for (; r < max_rounds && s_ok; ++r) {
@@ -686,9 +797,21 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         drain_memory();
         __syncthreads();
         if (threadIdx.x == 0) {
+            // Every kYieldEvery rounds (the same rounds in every block) the
+            // lead publishes the host's yield word before the barrier and
+            // every block reads it after: all stop together, before deciding
+            // the next round, and the next launch decides it.
+            const bool chk = s_ys && ((r + 1) & (kYieldEvery - 1)) == 0;
+            if (chk && lead) {
+                st(&RS->yield_req, __hip_atomic_load(s_ys, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_SYSTEM));
+                drain_memory();
+            }
             const bool bar = grid_arrive_wait(B, gen_local);
             if (!bar) s_fail = 1;
-            s_ok = bar && decide_round(C, p ^ 1, lead, sR, L, P.prof);
+            const bool y = bar && chk && ld(&RS->yield_req) != 0;
+            if (y) s_y = 1;
+            s_ok = bar && !y && decide_round(C, p ^ 1, lead, sR, L, P.prof);
         }
         __syncthreads();
         if (prof && lead) {
@@ -705,13 +828,15 @@ __global__ __launch_bounds__(kPBlock) void k_peel_persistent(PeelArgs P, GridBar
         }
         p ^= 1;
     }
-    if (s_fail) break;
+    if (s_fail || s_y) break;
+    p = -1;
     }
     flush_stats(C, upd, visits, unb, touch);
     if (lead) {
         L.store(C);
-        st(&C->pad, p);
         for (int k = 0; k < 6; ++k) st(&C->prof[k], ld(&C->prof[k]) + acc[k]);
+        st(&RS->yielded, s_y);
+        st(&RS->resume_p, s_y ? p : -1);
     }
 }
 
@@ -882,8 +1007,8 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
                      : peel_grid(r.tp, cus, occ * cus);
     }
 
-    std::unique_lock<std::mutex> coop_lock(coop_mutex(), std::defer_lock);
-    if (persistent) coop_lock.lock();
+    std::unique_ptr<CoopTurn> turn;
+    if (persistent) turn.reset(new CoopTurn(m));
     hipEvent_t ev0, ev1;  // around each peel launch: the kernel's device time
     BT_HIP(hipEventCreate(&ev0));
     BT_HIP(hipEventCreate(&ev1));
@@ -896,33 +1021,51 @@ void peel(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *phi_out,
     } ev_free{ev0, ev1};
     if (persistent) {
         // One launch: the kernel rebuilds the active set itself whenever it
-        // runs dry and stops when no edge remains.
+        // runs dry and stops when no edge remains; or, when a lighter peel
+        // waits for the device, it stops between two rounds and is launched
+        // again, to decide the next round, once that peel has had its turn.
+        // BT_PEEL_YIELD=1 makes every launch stop at its first check (a test
+        // of the resume path).
+        const char *yv = std::getenv("BT_PEEL_YIELD");
+        const bool force_yield = yv && std::atoi(yv) == 1;
         RefillState rs0{};
         rs0.min = INT_MAX;
         rs0.cur = -1;  // all edges, in id order
         rs0.n_all = m;
+        rs0.resume_p = -1;
+        rs0.yield_src = reinterpret_cast<u64>(turn->yield_word(force_yield));
         RefillState *drs = ws.get<RefillState>("peel_refill_state", 1);
         BT_HIP(hipMemcpyAsync(drs, &rs0, sizeof rs0, hipMemcpyHostToDevice, s));
         RefillArgs RA{drs, {glist[0], glist[1]}, min_level, r.tp.active_min};
         int64_t max_rounds = 4 * m + 64;
         int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
         void *args[] = {&P, &bar, &max_rounds, &prof, &RA};
-        BT_HIP(hipEventRecord(ev0, s));
-        BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
-                                          dim3(kPBlock), args, 0, s));
-        BT_HIP(hipEventRecord(ev1, s));
-        int32_t fail = 0;
-        BT_HIP(hipMemcpyAsync(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost, s));
-        BT_HIP(hipMemcpyAsync(&rs0, drs, sizeof rs0, hipMemcpyDeviceToHost, s));
-        BT_HIP(hipStreamSynchronize(s));
-        float t = 0.f;
-        BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
-        pc.kernel_ms += t;
-        pc.launches += 1;
-        if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
-        if (!rs0.done) throw Error{BT_EDEVICE, "peel stopped early"};
-        if (verbose)
-            std::fprintf(stderr, "[peel] one launch: %.1f ms\n", (double)t);
+        for (int64_t launch = 0;; ++launch) {
+            // A launch that yields has run kYieldEvery rounds.
+            if (launch * kYieldEvery > max_rounds)
+                throw Error{BT_EDEVICE, "peel made no progress"};
+            if (launch > 0) zero_bytes(bar, sizeof(GridBar), s);
+            BT_HIP(hipEventRecord(ev0, s));
+            BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_persistent, dim3(pblocks),
+                                              dim3(kPBlock), args, 0, s));
+            BT_HIP(hipEventRecord(ev1, s));
+            int32_t fail = 0;
+            BT_HIP(hipMemcpyAsync(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost, s));
+            BT_HIP(hipMemcpyAsync(&rs0, drs, sizeof rs0, hipMemcpyDeviceToHost, s));
+            BT_HIP(hipStreamSynchronize(s));
+            float t = 0.f;
+            BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
+            pc.kernel_ms += t;
+            pc.launches += 1;
+            if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
+            if (verbose)
+                std::fprintf(stderr, "[peel] launch %lld: %.1f ms%s\n", (long long)launch,
+                             (double)t, rs0.yielded ? " (yielded)" : "");
+            if (rs0.done) break;
+            if (!rs0.yielded) throw Error{BT_EDEVICE, "peel stopped early"};
+            pc.yields += 1;
+            turn->requeue();
+        }
     } else {
     int64_t n_all = m;
     int cur = -1;  // -1: all edges, in id order

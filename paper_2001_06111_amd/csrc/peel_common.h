@@ -19,8 +19,30 @@ namespace bt {
 // Cooperative peel kernels hold every CU until their last round; two of
 // them at once (from different threads or engine slots) could each wait at
 // a grid barrier for blocks the other keeps from being scheduled.  They
-// therefore run one at a time in the process (peel.hip holds the lock).
-std::mutex &coop_mutex();
+// therefore take turns in the process, in the order they asked.  While a
+// turn is held, a waiter whose batch has fewer than 1/8 of the holder's
+// edges raises the holder's yield word (pinned host memory that the kernel
+// reads); the single-graph persistent peel answers at its next rebuild of
+// the active set by ending its launch, and its host thread queues again and
+// relaunches from the state left in device memory.  The batch peel never
+// yields: its batches are the small ones.
+class CoopTurn {
+  public:
+    explicit CoopTurn(int64_t weight);  // blocks until this turn comes
+    ~CoopTurn();
+    CoopTurn(const CoopTurn &) = delete;
+    CoopTurn &operator=(const CoopTurn &) = delete;
+    // Device address of the yield word (nonzero: a lighter peel waits).
+    // With force, a word that always reads 1, for tests of the resume path.
+    const int32_t *yield_word(bool force) const;
+    // Gives the device up, queues behind every current waiter and returns
+    // when the turn comes again.
+    void requeue();
+
+  private:
+    uint64_t ticket_ = 0;
+    int64_t weight_ = 0;
+};
 
 namespace {
 

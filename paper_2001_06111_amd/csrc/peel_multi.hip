@@ -524,7 +524,7 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
                             : peel_grid(r.tp, cus, occ * cus);
     int64_t max_rounds = 8 * m + 64;
     int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
-    std::lock_guard<std::mutex> coop_lock(coop_mutex());
+    CoopTurn turn(m);
     hipEvent_t ev0, ev1;
     BT_HIP(hipEventCreate(&ev0));
     BT_HIP(hipEventCreate(&ev1));

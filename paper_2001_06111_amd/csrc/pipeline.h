@@ -138,6 +138,7 @@ struct PeelCounters {
     int64_t touched = 0;            // live wedges visited in phase B (L_touch)
     double kernel_ms = 0;  // HIP-event time of the peel kernel launches
     int64_t launches = 0;
+    int64_t yields = 0;  // launches that ended early to give the device to a lighter peel
 };
 // One round of a traced peel (only rounds that remove edges): its level,
 // the edges it removed, and every support and bloom number after it.

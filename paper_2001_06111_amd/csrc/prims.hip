@@ -35,6 +35,7 @@ struct Hook {
 struct Block {
     Hook hook;
     size_t bytes;
+    hipStream_t stream;  // stream-ordered block (nullptr: device-wide)
 };
 std::mutex &alloc_mu() {
     static std::mutex *m = new std::mutex();  // never destroyed: outlives static teardown
@@ -54,7 +55,7 @@ void set_allocator(bt_alloc_fn a, bt_free_fn f, void *ctx) {
     g_hook = Hook{a, f, ctx};
 }
 
-void *device_alloc(size_t bytes) {
+void *device_alloc(size_t bytes, hipStream_t stream) {
     void *p = nullptr;
     if (bytes == 0) bytes = 256;
     Hook h;
@@ -68,7 +69,7 @@ void *device_alloc(size_t bytes) {
             throw Error{BT_ENOMEM, "device allocation of " + std::to_string(bytes) +
                                        " bytes failed (allocator hook returned NULL)"};
     } else {
-        hipError_t e = hipMalloc(&p, bytes);
+        hipError_t e = stream ? hipMallocAsync(&p, bytes, stream) : hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             throw Error{BT_ENOMEM, "device allocation of " + std::to_string(bytes) +
@@ -76,7 +77,7 @@ void *device_alloc(size_t bytes) {
         }
     }
     std::lock_guard<std::mutex> lk(alloc_mu());
-    live_blocks()[p] = Block{h, bytes};
+    live_blocks()[p] = Block{h, bytes, stream};
     return p;
 }
 
@@ -94,14 +95,31 @@ void device_free(void *p) {
     if (b.hook.free) {
         // A hook may hand the block out again at once (a caching allocator),
         // so no kernel of the library may still use it.
-        (void)hipDeviceSynchronize();
+        if (b.stream)
+            (void)hipStreamSynchronize(b.stream);
+        else
+            (void)hipDeviceSynchronize();
         b.hook.free(p, b.bytes, b.hook.ctx);
+    } else if (b.stream) {
+        (void)hipFreeAsync(p, b.stream);
     } else {
         (void)hipFree(p);
     }
 }
 
-Workspace::~Workspace() { release(); }
+Workspace::~Workspace() { close(); }
+
+void Workspace::close() {
+    release();
+    if (!stream_) return;
+    (void)hipStreamSynchronize(stream_);
+    for (int64_t *h : old_host_) (void)hipHostFree(h);
+    old_host_.clear();
+    if (host_) (void)hipHostFree(host_);
+    host_ = nullptr;
+    host_cap_ = 0;
+    stream_ = nullptr;
+}
 
 void Workspace::use_arena(void *base, size_t cap, int64_t *host, int n_host) {
     release();
@@ -141,7 +159,7 @@ void *Workspace::get(const char *name, size_t bytes) {
                 device_free(b.ptr);
                 b.ptr = nullptr;
                 b.cap = 0;
-                b.ptr = device_alloc(bytes + bytes / 8);
+                b.ptr = device_alloc(bytes + bytes / 8, stream_);
                 b.cap = bytes + bytes / 8;
             }
             return b.ptr;
@@ -149,7 +167,7 @@ void *Workspace::get(const char *name, size_t bytes) {
     }
     Buf nb;
     nb.name = name;
-    nb.ptr = device_alloc(bytes);
+    nb.ptr = device_alloc(bytes, stream_);
     nb.cap = bytes;
     bufs_.push_back(nb);
     return nb.ptr;
@@ -165,6 +183,7 @@ void Workspace::release() {
     graphs.clear();
     for (auto &b : bufs_) device_free(b.ptr);
     bufs_.clear();
+    if (stream_) return;  // host scratch stays until the destructor
     if (host_) (void)hipHostFree(host_);
     host_ = nullptr;
     host_cap_ = 0;
@@ -183,7 +202,12 @@ int64_t *Workspace::host(int n) {
         return host_;
     }
     if (n > host_cap_) {
-        if (host_) (void)hipHostFree(host_);
+        if (host_) {
+            if (stream_)
+                old_host_.push_back(host_);
+            else
+                (void)hipHostFree(host_);
+        }
         host_ = nullptr;
         host_cap_ = 0;
         const int cap = n > 4096 ? n : 4096;
