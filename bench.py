@@ -299,6 +299,17 @@ def serve_compare(seconds, graphs, big, arrivals, slots):
     lat_p, lat_s = done_plain - arrive, done_srv - arrive
     log(f"serve: plain p99 {np.percentile(lat_p, 99):.3f}s served p99 "
         f"{np.percentile(lat_s, 99):.3f}s")
+    # The engine's size classes: below 2^14 edges, below 2^19, larger.
+    m = np.array([g.m for g in graph])
+    by_class = {}
+    for name, sel in (("small", m < (1 << 14)), ("medium", (m >= (1 << 14)) & (m < (1 << 19))),
+                      ("large", m >= (1 << 19))):
+        if sel.any():
+            by_class[name] = {"requests": int(sel.sum()),
+                              "served_p50_s": float(np.percentile(lat_s[sel], 50)),
+                              "served_p99_s": float(np.percentile(lat_s[sel], 99)),
+                              "plain_p50_s": float(np.percentile(lat_p[sel], 50)),
+                              "plain_p99_s": float(np.percentile(lat_p[sel], 99))}
     return {"workload": f"Poisson 200/s for {seconds:g} s: 95% graphs of the 4,096-graph pool, "
                         f"5% 2M-edge graphs of a pool of 32 (50k x 200k, exponent 2.0)",
             "requests": len(graph), "big_requests": sum(1 for _, k, _ in arrivals if k == "big"),
@@ -309,7 +320,8 @@ def serve_compare(seconds, graphs, big, arrivals, slots):
             "plain_p99_s": float(np.percentile(lat_p, 99)),
             "served_graphs_per_s": len(graph) / done_srv.max(),
             "plain_graphs_per_s": len(graph) / done_plain.max(),
-            "served_batches": est["batches"], "all_status_ok": ok,
+            "served_batches": est["batches"], "peel_yields": est["peel_yields"],
+            "by_class": by_class, "all_status_ok": ok,
             "every_result_equals_plain": bool(same)}
 
 

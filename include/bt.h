@@ -355,7 +355,7 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   the oldest one that fit the budget left by the other slots, and
  *   decomposes them as one batch (bt_decompose_batch semantics).  A batch
  *   holds one size class: below 2^14 edges, below 2^19, or larger (at most
- *   four of those at a time).  The smallest class queued goes first, unless
+ *   eight of those at a time).  The smallest class queued goes first, unless
  *   the oldest request of a larger class has waited 10 s.  Requests that
  *   arrive meanwhile go to the next free slot, so batches overlap on the
  *   device.

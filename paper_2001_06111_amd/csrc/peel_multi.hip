@@ -54,9 +54,15 @@ struct MultiCtl {
     Counter updates, bloom_visits;
     Counter touched;  // live wedges visited in phase B
     Counter left;  // graphs not done
-    u64 rounds;
+    u64 rounds;    // rounds run so far (a resumed launch starts at this round)
     u64 prof[5];   // BT_PEEL_PROFILE=1: block-0 clock ticks (decide, A, bar, B, bar)
+    u64 yield_src;      // address of the host-written yield word (0: none)
+    int32_t yield_req;  // the yield word as the lead last read it
+    int32_t yielded;    // set when the launch ended early to give way
 };
+
+// Every kMultiYieldEvery rounds the lead reads the host's yield word.
+constexpr int64_t kMultiYieldEvery = 32;
 
 struct MultiArgs {
     MultiCtl *ctl;
@@ -334,8 +340,9 @@ __device__ __forceinline__ void multi_phase_b(const PeelArgs &P, const MultiArgs
 __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M, GridBar *B,
                                                         int64_t max_rounds, int prof) {
     MultiCtl *C = M.ctl;
-    __shared__ u64 s_nf, s_ngth, s_ntc, s_left;
-    __shared__ int s_ok;
+    __shared__ u64 s_nf, s_ngth, s_ntc, s_left, s_r0;
+    __shared__ int s_ok, s_y;
+    __shared__ const int32_t *s_ys;
     u64 gen_local = 0;
     const int64_t wid = (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
     const int64_t nwaves = (int64_t)gridDim.x * (kPBlock / kWave);
@@ -343,13 +350,18 @@ __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M,
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     u64 upd = 0, visits = 0, touch = 0;
     if (threadIdx.x == 0) {
+        // A launch resumes at the round where the previous one yielded.
+        s_r0 = ld(&C->rounds);
         s_left = ld(&C->left.v);
-        s_nf = ld(&C->nf[0].v);
-        s_ngth = ld(&C->ngth[0].v);
+        s_nf = ld(&C->nf[s_r0 & 1].v);
+        s_ngth = ld(&C->ngth[s_r0 & 1].v);
+        s_ys = reinterpret_cast<const int32_t *>(ld(&C->yield_src));
         s_ok = 1;
+        s_y = 0;
     }
+    if (lead) st(&C->yielded, 0);
     __syncthreads();
-    int64_t r = 0;
+    int64_t r = (int64_t)s_r0;
     for (; r < max_rounds && s_left > 0 && s_ok; ++r) {
         const int p = (int)(r & 1), q = p ^ 1;
         const u64 nf = s_nf, ngth = s_ngth;
@@ -377,10 +389,20 @@ __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M,
         drain_memory();
         __syncthreads();
         if (threadIdx.x == 0) {
+            // Every kMultiYieldEvery rounds the lead publishes the host's
+            // yield word before the barrier and every block reads it after,
+            // so all blocks stop after the same round.
+            const bool chk = s_ys && ((r + 1) % kMultiYieldEvery) == 0;
+            if (chk && lead) {
+                st(&C->yield_req, __hip_atomic_load(s_ys, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_SYSTEM));
+                drain_memory();
+            }
             s_ok = grid_arrive_wait(B, gen_local);
             s_left = ld(&C->left.v);
             s_nf = ld(&C->nf[q].v);
             s_ngth = ld(&C->ngth[q].v);
+            s_y = s_ok && chk && ld(&C->yield_req) != 0;
         }
         __syncthreads();
         if (prof && lead) {
@@ -389,6 +411,11 @@ __global__ __launch_bounds__(kPBlock) void k_peel_multi(PeelArgs P, MultiArgs M,
             C->prof[1] += t2 - t1;
             C->prof[2] += t3 - t2;
             C->prof[4] += t4 - t3;
+        }
+        if (s_y) {
+            ++r;
+            if (lead && s_left > 0) st(&C->yielded, 1);
+            break;
         }
     }
     upd = wave_sum(upd);
@@ -507,8 +534,14 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
         left += mg > 0 ? 1 : 0;
     }
     BT_HIP(hipMemcpyAsync(M.gs, gs.data(), sizeof(GState) * ng, hipMemcpyHostToDevice, s));
+    // The turn on the device comes first: the control block carries the
+    // address of its yield word.  A batch peel yields to one of under 1/8 of
+    // its edges; BT_PEEL_YIELD=1 makes it stop at every check instead.
+    CoopTurn turn(m);
+    const char *yv = std::getenv("BT_PEEL_YIELD");
     MultiCtl mc{};
     mc.left.v = (u64)left;
+    mc.yield_src = reinterpret_cast<u64>(turn.yield_word(yv && std::atoi(yv) == 1));
     BT_HIP(hipMemcpyAsync(M.ctl, &mc, sizeof mc, hipMemcpyHostToDevice, s));
     GridBar *bar = ws.get<GridBar>("peel_bar", 1);
     zero_bytes(bar, sizeof(GridBar), s);
@@ -524,29 +557,42 @@ void peel_multi(const RankCSR &r, IndexArrays &ix, int64_t *sup_out, int64_t *ph
                             : peel_grid(r.tp, cus, occ * cus);
     int64_t max_rounds = 8 * m + 64;
     int prof = std::getenv("BT_PEEL_PROFILE") ? 1 : 0;
-    CoopTurn turn(m);
     hipEvent_t ev0, ev1;
     BT_HIP(hipEventCreate(&ev0));
     BT_HIP(hipEventCreate(&ev1));
-    BT_HIP(hipEventRecord(ev0, s));
+    struct EvFree {
+        hipEvent_t a, b;
+        ~EvFree() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev_free{ev0, ev1};
     void *args[] = {&P, &M, &bar, &max_rounds, &prof};
-    BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_multi, dim3(pblocks), dim3(kPBlock),
-                                      args, 0, s));
-    BT_HIP(hipEventRecord(ev1, s));
     MultiCtl hc{};
-    int32_t fail = 0;
-    BT_HIP(hipMemcpyAsync(&hc, M.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
-    BT_HIP(hipMemcpyAsync(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost, s));
+    for (;;) {
+        BT_HIP(hipEventRecord(ev0, s));
+        BT_HIP(hipLaunchCooperativeKernel((const void *)k_peel_multi, dim3(pblocks),
+                                          dim3(kPBlock), args, 0, s));
+        BT_HIP(hipEventRecord(ev1, s));
+        int32_t fail = 0;
+        BT_HIP(hipMemcpyAsync(&hc, M.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
+        BT_HIP(hipMemcpyAsync(&fail, &bar->fail, sizeof fail, hipMemcpyDeviceToHost, s));
+        BT_HIP(hipStreamSynchronize(s));
+        float t = 0.f;
+        BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
+        pc.kernel_ms += t;
+        pc.launches += 1;
+        if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
+        if (hc.left.v == 0) break;
+        if (!hc.yielded) throw Error{BT_EDEVICE, "batch peel stopped early"};
+        // Each launch that yields has run kMultiYieldEvery rounds.
+        if ((int64_t)hc.rounds >= max_rounds) throw Error{BT_EDEVICE, "batch peel made no progress"};
+        pc.yields += 1;
+        turn.requeue();
+        zero_bytes(bar, sizeof(GridBar), s);
+    }
     BT_HIP(hipMemcpyAsync(gs.data(), M.gs, sizeof(GState) * ng, hipMemcpyDeviceToHost, s));
     BT_HIP(hipStreamSynchronize(s));
-    float t = 0.f;
-    BT_HIP(hipEventElapsedTime(&t, ev0, ev1));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    if (fail) throw Error{BT_EDEVICE, "peel grid barrier timed out"};
-    if (hc.left.v != 0) throw Error{BT_EDEVICE, "batch peel stopped early"};
-    pc.kernel_ms += t;
-    pc.launches += 1;
     pc.rounds = (int64_t)hc.rounds;
     pc.updates = (int64_t)hc.updates.v;
     pc.bloom_visits = (int64_t)hc.bloom_visits.v;

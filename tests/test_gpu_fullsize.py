@@ -103,6 +103,27 @@ def test_request_graph_2m_digest():
         eng.bt_engine_destroy()
 
 
+def test_request_graphs_digests():
+    """Every 2M-edge request graph with an oracle digest, decomposed four at
+    a time as one union (the serving engine's large-class batch, one shared
+    level): supports, totals and bitruss numbers equal the oracle's."""
+    per = GOLD.get("bigs", {}).get("per_graph", {})
+    js = sorted(int(j) for j in per)
+    if not js:
+        pytest.skip("no request-graph digests beyond graph 0")
+    for k in range(0, len(js), 4):
+        part = js[k:k + 4]
+        dgs = [binding.DeviceGraph.upload(synth.big_serving_graph(j)) for j in part]
+        sups, phis, _ = binding.bt_decompose_batch(dgs)
+        for j, sup, phi in zip(part, sups, phis):
+            want = per[str(j)]
+            assert want["generator_version"] == synth.GENERATOR_VERSION
+            assert int(sup.sum().item()) == 4 * want["butterflies"], j
+            assert sha(sup.cpu().numpy()) == want["sup_sha256"], j
+            assert sha(phi.cpu().numpy()) == want["phi_sha256"], j
+        del dgs, sups, phis
+
+
 @pytest.mark.slow
 @pytest.mark.timeout(1200)
 def test_pool4096_batched_digests():

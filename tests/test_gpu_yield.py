@@ -56,6 +56,26 @@ def test_forced_yield_in_progressive_passes(monkeypatch):
     assert torch.equal(phi0, phi1)
 
 
+def test_forced_yield_in_batch_peel(monkeypatch):
+    """The batch peel (each graph at its own level) resumes at the round
+    where it stopped: same numbers and the same rounds."""
+    gs = [synth.batch_graph(i) for i in range(40)]
+    dgs = [upload(g) for g in gs]
+    sups0, phis0, st0 = binding.bt_decompose_batch(dgs, stats=True)
+    monkeypatch.setenv("BT_PEEL_YIELD", "1")
+    sups1, phis1, st1 = binding.bt_decompose_batch(dgs, stats=True)
+    monkeypatch.delenv("BT_PEEL_YIELD")
+    assert st0["peel_yields"] == 0
+    assert st1["peel_yields"] >= 1 and st1["peel_launches"] == st0["peel_launches"] + st1["peel_yields"]
+    for k in ("rounds", "levels", "support_updates", "bloom_visits", "wedge_visits", "max_phi"):
+        assert st1[k] == st0[k], k
+    for i, g in enumerate(gs):
+        assert torch.equal(phis0[i], phis1[i]) and torch.equal(sups0[i], sups1[i]), g.name
+    for i in (0, 1, 2):
+        osup, _, ophi = oracle_all(gs[i])
+        assert np.array_equal(phis1[i].cpu().numpy(), ophi)
+
+
 def test_engine_small_batches_run_while_a_large_request_peels():
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "digests.json")))
     big = synth.big_serving_graph(0)
