@@ -12,8 +12,8 @@
 // class has waited kLargeWaitS.  Requests that arrive while batches run are
 // admitted by the next free slot: with two slots (the default) one slot
 // counts and builds the index of its batch on the device while the other
-// slot's batch peels.  Each result equals the plain single-graph
-// decomposition of the request.
+// slot's batch peels, and one slot is kept for the small class.  Each
+// result equals the plain single-graph decomposition of the request.
 //
 // Memory.  A slot's workspace is cached between its batches, so the budget
 // covers what every slot holds plus what its running batch may still add:
@@ -72,10 +72,21 @@ constexpr int32_t kLargePerBatch = 8;
 // larger ones).
 constexpr double kLargeWaitS = 10.0;
 constexpr int kDefaultSlots = 2;
+// Weights of a batch's turns on the device, by size class (each class's
+// bound on its graphs' edges; the large one well above 8x the medium): a
+// waiting batch of a smaller class makes a running peel of a larger class
+// yield.
+constexpr int64_t kClassTurnWeight[kClasses] = {int64_t(1) << 14, int64_t(1) << 19,
+                                                int64_t(1) << 23};
+// With two or more slots, one is always left for the small class: a slot
+// starts a batch of a larger class only while fewer than slots - 1 other
+// slots run one, so small requests never queue behind two long batches
+// (their peels take the device from a running one of 8x their edges).
 
 struct Slot {
     int64_t held = 0;      // workspace bytes (written by the slot's own thread)
     int64_t res = 0;       // bytes its running batch may still add
+    int cls = -1;          // size class of the running batch (-1: idle)
     bool busy = false;
     bool release = false;  // asked to free its cached workspace while idle
 };
@@ -116,7 +127,7 @@ struct bt_engine {
     int64_t peak_held = 0;       // largest sum of held seen
 
     void worker_loop(int slot);
-    int pick_class() const;
+    int pick_class(bool larger_ok) const;
     const Request *first_of(int cls) const;
     int64_t committed_except(int s) const;
     void note_peaks();
@@ -131,7 +142,10 @@ const Request *bt_engine::first_of(int cls) const {
 // The class of the next batch (call with mu held and the queue non-empty):
 // the largest class whose oldest request has waited kLargeWaitS, else the
 // smallest class present.
-int bt_engine::pick_class() const {
+// The class of the next batch, or -1 when no queued request may start now
+// (larger_ok false: only the small class may).
+int bt_engine::pick_class(bool larger_ok) const {
+    if (!larger_ok) return first_of(0) ? 0 : -1;
     const auto now = std::chrono::steady_clock::now();
     for (int c = kClasses - 1; c > 0; --c) {
         const Request *r = first_of(c);
@@ -139,7 +153,7 @@ int bt_engine::pick_class() const {
     }
     for (int c = 0; c < kClasses; ++c)
         if (first_of(c)) return c;
-    return 0;
+    return -1;
 }
 
 int64_t bt_engine::committed_except(int s) const {
@@ -168,6 +182,7 @@ void bt_engine::worker_loop(int slot) {
     while (true) {
         std::vector<Request> batch;
         int64_t bytes = 0, held0 = 0;
+        int batch_cls = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
             Slot &me = slots[(size_t)slot];
@@ -176,7 +191,11 @@ void bt_engine::worker_loop(int slot) {
                 if (stop) return true;
                 if (me.release) return true;
                 if (queue.empty()) return false;
-                cls = pick_class();
+                int larger = 0;  // other slots running a batch of a larger class
+                for (size_t i = 0; i < slots.size(); ++i)
+                    if ((int)i != slot && slots[i].busy && slots[i].cls > 0) ++larger;
+                cls = pick_class(slots.size() < 2 || larger < (int)slots.size() - 1);
+                if (cls < 0) return false;
                 const int64_t need = first_of(cls)->bytes;
                 const int64_t others = committed_except(slot);
                 if (others + need <= budget) return true;
@@ -235,6 +254,8 @@ void bt_engine::worker_loop(int slot) {
             held0 = me.held;
             me.res = bytes;
             me.busy = true;
+            me.cls = cls;
+            batch_cls = cls;
             running += (int64_t)batch.size();
             batches += 1;
             admitted += (int64_t)batch.size();
@@ -268,6 +289,7 @@ void bt_engine::worker_loop(int slot) {
         };
         std::vector<Done> out;
         bt_stats bst{};
+        set_turn_weight(kClassTurnWeight[batch_cls]);
         try {
             decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), &bst,
                                  ws, s, &on_sized);
@@ -295,6 +317,7 @@ void bt_engine::worker_loop(int slot) {
             me.held = held_now;
             me.res = 0;
             me.busy = false;
+            me.cls = -1;
             note_peaks();
             peel_yields += bst.peel_yields;
             if (verbose)

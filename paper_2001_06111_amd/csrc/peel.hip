@@ -90,7 +90,7 @@ void update_yield(Gate &g) {
     if (!g.word) return;
     static const bool verbose = std::getenv("BT_PEEL_VERBOSE") != nullptr;
     if (verbose && (g.word[0] != 0) != ask)
-        std::fprintf(stderr, "[peel] yield word %d (holder %lld edges, %zu waiting)\n", ask ? 1 : 0,
+        std::fprintf(stderr, "[peel] yield word %d (holder weight %lld, %zu waiting)\n", ask ? 1 : 0,
                      (long long)g.holder_weight, g.waiting.size());
     __atomic_store_n(&g.word[0], ask ? 1 : 0, __ATOMIC_RELEASE);
 }
@@ -108,7 +108,13 @@ void take_turn(Gate &g, std::unique_lock<std::mutex> &lk, uint64_t ticket, int64
 
 }  // namespace
 
-CoopTurn::CoopTurn(int64_t weight) : weight_(weight) {
+namespace {
+thread_local int64_t t_turn_weight = -1;
+}  // namespace
+
+void set_turn_weight(int64_t w) { t_turn_weight = w; }
+
+CoopTurn::CoopTurn(int64_t weight) : weight_(t_turn_weight >= 0 ? t_turn_weight : weight) {
     Gate &g = gate();
     std::unique_lock<std::mutex> lk(g.mu);
     if (!g.word) {

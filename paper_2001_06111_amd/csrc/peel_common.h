@@ -20,15 +20,16 @@ namespace bt {
 // them at once (from different threads or engine slots) could each wait at
 // a grid barrier for blocks the other keeps from being scheduled.  They
 // therefore take turns in the process, in the order they asked.  While a
-// turn is held, a waiter whose batch has fewer than 1/8 of the holder's
-// edges raises the holder's yield word (pinned host memory that the kernel
-// reads); the single-graph persistent peel answers at its next rebuild of
-// the active set by ending its launch, and its host thread queues again and
-// relaunches from the state left in device memory.  The batch peel never
-// yields: its batches are the small ones.
+// turn is held, a waiter that weighs under 1/8 of the holder raises the
+// holder's yield word (pinned host memory that the kernel reads every few
+// rounds); the peel kernel then ends its launch between two rounds, and its
+// host thread queues again and relaunches from the state left in device
+// memory.
 class CoopTurn {
   public:
-    explicit CoopTurn(int64_t weight);  // blocks until this turn comes
+    // Blocks until this turn comes.  The turn weighs `weight` (the peel's
+    // edges) unless the calling thread set another weight for its turns.
+    explicit CoopTurn(int64_t weight);
     ~CoopTurn();
     CoopTurn(const CoopTurn &) = delete;
     CoopTurn &operator=(const CoopTurn &) = delete;
@@ -91,7 +92,7 @@ struct PeelCtl {
     int32_t stall;
     int32_t thresh;     // active threshold T
     int32_t max_level;  // largest level at which edges were removed
-    int32_t pad;        // persistent kernel: parity of the next round
+    int32_t pad;
     u64 rounds, levels;
     u64 prof[6];        // persistent kernel, BT_PEEL_PROFILE=1: block-0 clock ticks
     // BT_PEEL_PROFILE=1: frontier pushes by twin (phase A) and survivor

@@ -154,6 +154,13 @@ using PeelTraceFn = std::function<void(const PeelTraceRound &)>;
 // marks (mark_fixed).  The first level is at least `min_level`.
 // `trace` (nullable): run the rounds one at a time from the host and report
 // each (small graphs; for inspection and tests).
+// The weight of this thread's later turns on the device for cooperative
+// peels (w < 0: each peel's edge count).  A waiting peel that weighs under
+// 1/8 of the running one makes it yield between two rounds.  The serving
+// engine weighs a batch by its size class, so a batch of a smaller class
+// always takes the device from a running one of a larger class.
+void set_turn_weight(int64_t w);
+
 struct PeelOptions {
     const int32_t *fixed = nullptr;
     int32_t min_level = 0;
