@@ -226,7 +226,8 @@ def single(name, g, reps, warmup, golden, variant=None, tau=None, traffic=None):
     d = sha_i64([phi.cpu().numpy()])
     want = golden.get(g.name, {}).get("phi_sha256")
     out = {"workload": g.name, "m": g.m, "seconds": t, "edges_per_s": g.m / t,
-           "wedges_per_s": st["wedges_po"] / t, "reps": reps,
+           "wedges_per_s": st["wedges_po"] / t, "reps": reps, "warmup": warmup,
+           "p50_s": t, "p99_s": ts[min(len(ts) - 1, int(0.99 * len(ts)))],
            "phi_check": "no-oracle-digest" if want is None else
            ("match" if want == d else "MISMATCH"),
            "phases_ms": {k: round(st[k], 3) for k in ("ms_prepare", "ms_count", "ms_link",

@@ -335,10 +335,11 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   per batch (0: 1024).  The peel of a batch holds most of the GPU, so the
  *   peels of different slots take turns; a second slot counts and builds
  *   the index of the next batch while one slot's batch peels, and when that
- *   batch has under 1/8 of the running peel's edges, the running peel (if
- *   it is the single-graph persistent peel of a large batch) ends its
- *   launch at its next rebuild of the active set, lets the smaller batch
- *   peel, and resumes where it stopped.
+ *   batch is of a smaller size class, the running peel ends its launch
+ *   between two rounds (within 32 rounds), lets the smaller batch peel,
+ *   and resumes where it stopped.  With two or more slots one is kept for
+ *   the small class: a slot starts a larger class's batch only while fewer
+ *   than slots - 1 others run one.
  *   Memory: the budget covers every slot's cached workspace plus what its
  *   running batch may still allocate (the submit-time estimate, replaced by
  *   the exact peel state once the batch's index is built); a slot frees its
