@@ -1,4 +1,4 @@
-"""Write tests/golden/digests.json from the CPU oracle.
+"""Write tests/golden/digests.json (and digests_requests.json) from the CPU oracle.
 
 For each seeded workload: SHA-256 of the oracle's int64 supports and int64
 bitruss numbers (little-endian, edge order = CSR position), the butterfly
@@ -12,8 +12,10 @@ Calls only `oracle` and the seeded generators.
 hub20m:vsF is the induced subgraph of the 20M-edge hub graph on a random
 fraction F of each layer's vertices (sampling seed 2027), the protocol of
 the paper's scalability experiments.  bigs:A-B adds request graphs A..B-1
-one at a time to the "bigs" entry (per-graph digests), so a long run can be
-stopped and resumed.
+one at a time to tests/golden/digests_requests.json (per-graph digests, a
+file of their own so that long runs of other workloads, which rewrite
+digests.json when they end, leave them alone); a run can be stopped and
+resumed.
 """
 import hashlib
 import json
@@ -31,6 +33,7 @@ from paper_2001_06111_amd import synth  # noqa: E402
 
 VS_SEED = 2027
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "digests.json")
+OUT_REQ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "digests_requests.json")
 
 
 def sha(a):
@@ -71,19 +74,22 @@ def main(args):
                             "generator_version": synth.GENERATOR_VERSION}
         elif a.startswith("bigs:"):
             lo, hi = (int(x) for x in a.split(":")[1].split("-"))
-            ent = data.setdefault("bigs", {"per_graph": {}})
+            req = json.load(open(OUT_REQ)) if os.path.exists(OUT_REQ) else {}
+            ent = req.setdefault("per_graph", {})
             for j in range(lo, hi):
-                if str(j) in ent["per_graph"]:
+                if str(j) in ent:
                     continue
                 g = synth.big_serving_graph(j)
                 sup, bf, phi, st, dt = run(g)
-                ent["per_graph"][str(j)] = {"m": g.m, "butterflies": bf, "sup_sha256": sha(sup),
-                                            "phi_sha256": sha(phi), "max_phi": int(phi.max()),
-                                            "oracle_seconds": round(dt, 1),
-                                            "oracle_threads": oracle.max_threads(),
-                                            "generator_version": synth.GENERATOR_VERSION}
-                json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+                ent[str(j)] = {"m": g.m, "butterflies": bf, "sup_sha256": sha(sup),
+                               "phi_sha256": sha(phi), "max_phi": int(phi.max()),
+                               "oracle_seconds": round(dt, 1),
+                               "oracle_threads": oracle.max_threads(),
+                               "generator_version": synth.GENERATOR_VERSION}
+                json.dump(req, open(OUT_REQ, "w"), indent=1, sort_keys=True)
                 print(f"big {j}: m={g.m} bf={bf} {dt:.0f}s", flush=True)
+            print("wrote", a, flush=True)
+            continue
         elif a == "hub20m:sup":
             # Support counting only: the oracle's peel would take hours here.
             g = synth.plain_hub_20m()
