@@ -509,7 +509,13 @@ void batch_range(const bt_csr *gs, int32_t a, int32_t b, int64_t *const *sup_out
 
 // Batches are cut at about kBatchEdges edges so that each union stays well
 // inside the index limits; an oversized union is split in halves.
+// BT_BATCH_EDGES_LOG2 (16..30) sets another cut, for measurements.
 constexpr int64_t kBatchEdges = int64_t(1) << 26;
+int64_t batch_edges() {
+    const char *v = std::getenv("BT_BATCH_EDGES_LOG2");
+    const int l = v ? std::atoi(v) : 0;
+    return l >= 16 && l <= 30 ? int64_t(1) << l : kBatchEdges;
+}
 
 }  // namespace
 
@@ -533,11 +539,12 @@ void decompose_batch_impl(const bt_csr *gs, int32_t n, int64_t *const *sup_out,
         s2[(size_t)i] = sup_out ? sup_out[o] : nullptr;
         p2[(size_t)i] = phi_out[o];
     }
+    const int64_t cut = batch_edges();
     int32_t a = 0;
     while (a < n) {
         int32_t b = a;
         int64_t m = 0;
-        while (b < n && (b == a || m + g2[(size_t)b].m <= kBatchEdges)) m += g2[(size_t)b++].m;
+        while (b < n && (b == a || m + g2[(size_t)b].m <= cut)) m += g2[(size_t)b++].m;
         // The size report is exact only when one union holds the whole batch.
         batch_range(g2.data(), a, b, sup_out ? s2.data() : nullptr, p2.data(), stats, ws, s,
                     a == 0 && b == n ? on_sized : nullptr);
