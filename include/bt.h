@@ -330,7 +330,9 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  * Serving engine with continuous batching (for request streams).
  *
  * bt_engine_create: `slots` worker slots (0: 2), each with its own HIP
- *   stream and cached workspace; `hbm_budget` bytes of device memory for
+ *   stream, cached workspace and worker thread; slots = -1 creates a
+ *   caller-driven engine instead (one slot, no threads: see
+ *   bt_engine_step); `hbm_budget` bytes of device memory for
  *   the engine (0: half of the free memory); at most `max_batch` requests
  *   per batch (0: 1024).  The peel of a batch holds most of the GPU, so the
  *   peels of different slots take turns; a second slot counts and builds
@@ -360,9 +362,17 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   the oldest request of a larger class has waited 10 s.  Requests that
  *   arrive meanwhile go to the next free slot, so batches overlap on the
  *   device.
+ * bt_engine_step: caller-driven engines only (else BT_EINVAL): admits the
+ *   batch a free slot would admit now and decomposes it on the calling
+ *   thread, on the engine's own stream; *n_done (nullable) receives the
+ *   number of requests it completed (0: nothing was queued).  Their
+ *   (id, status) pairs are then ready for bt_engine_poll.  Steps from
+ *   several threads take turns.
  * bt_engine_poll: moves up to `cap` completed (id, status) pairs to the
  *   caller's host arrays; *n_done receives how many.
- * bt_engine_drain: blocks until every submitted request has completed.
+ * bt_engine_drain: blocks until every submitted request has completed (a
+ *   caller-driven engine steps on the calling thread until its queue is
+ *   empty).
  * bt_engine_memory: the budget, the bytes the slots' workspaces hold now,
  *   the largest such sum so far, and the largest sum of held plus reserved
  *   bytes so far (which admission keeps within the budget).
@@ -374,6 +384,7 @@ bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
                            bt_engine **out);
 bt_status bt_engine_submit(bt_engine *engine, const bt_csr *g, int64_t *sup_out,
                            int64_t *phi_out, uint64_t id);
+bt_status bt_engine_step(bt_engine *engine, int32_t *n_done);
 bt_status bt_engine_poll(bt_engine *engine, uint64_t *ids, int32_t *status, int32_t cap,
                          int32_t *n_done);
 bt_status bt_engine_drain(bt_engine *engine);

@@ -447,8 +447,8 @@ def bt_version() -> str:
 
 # --- serving engine ----------------------------------------------------------
 
-EXPORTED += ["bt_engine_create", "bt_engine_submit", "bt_engine_poll", "bt_engine_drain",
-             "bt_engine_stats", "bt_engine_memory", "bt_engine_destroy"]
+EXPORTED += ["bt_engine_create", "bt_engine_submit", "bt_engine_step", "bt_engine_poll",
+             "bt_engine_drain", "bt_engine_stats", "bt_engine_memory", "bt_engine_destroy"]
 
 
 def _engine_lib():
@@ -459,13 +459,14 @@ def _engine_lib():
         L.bt_engine_submit.argtypes = [p, ctypes.POINTER(bt_csr), p, p, u64]
         L.bt_engine_poll.argtypes = [p, ctypes.POINTER(u64), ctypes.POINTER(i32), i32,
                                      ctypes.POINTER(i32)]
+        L.bt_engine_step.argtypes = [p, ctypes.POINTER(i32)]
         L.bt_engine_drain.argtypes = [p]
         L.bt_engine_stats.argtypes = [p] + [ctypes.POINTER(i64)] * 4
         L.bt_engine_memory.argtypes = [p] + [ctypes.POINTER(i64)] * 4
         L.bt_engine_destroy.argtypes = [p]
         L.bt_engine_destroy.restype = None
-        for n in ("bt_engine_create", "bt_engine_submit", "bt_engine_poll", "bt_engine_drain",
-                  "bt_engine_stats", "bt_engine_memory"):
+        for n in ("bt_engine_create", "bt_engine_submit", "bt_engine_step", "bt_engine_poll",
+                  "bt_engine_drain", "bt_engine_stats", "bt_engine_memory"):
             getattr(L, n).restype = ctypes.c_int
         L._engine_ready = True
     return L
@@ -513,6 +514,13 @@ class BtEngine:
             self.results[rid] = (s, sup, phi)
             out.append((rid, s))
         return out
+
+    def bt_engine_step(self):
+        """Caller-driven engines (slots=-1): run one batch on this thread;
+        returns how many requests it completed (0: none queued)."""
+        n = ctypes.c_int32(0)
+        _check(_engine_lib().bt_engine_step(self._h, ctypes.byref(n)))
+        return n.value
 
     def bt_engine_drain(self):
         _check(_engine_lib().bt_engine_drain(self._h))

@@ -91,6 +91,15 @@ struct Slot {
     bool release = false;  // asked to free its cached workspace while idle
 };
 
+// An admitted batch: its requests, their estimates, the slot's holdings at
+// admission and the batch's size class.
+struct Batch {
+    std::vector<Request> reqs;
+    int64_t bytes = 0;
+    int64_t held0 = 0;
+    int cls = 0;
+};
+
 }  // namespace
 }  // namespace bt
 
@@ -125,8 +134,18 @@ struct bt_engine {
     }
     int64_t peak_committed = 0;  // largest sum of held + res seen
     int64_t peak_held = 0;       // largest sum of held seen
+    // Caller-driven engine (created with slots = -1): no worker threads;
+    // bt_engine_step runs one batch of its single slot on the caller's
+    // thread, on this stream and workspace.
+    bool manual = false;
+    std::mutex step_mu;  // one step at a time
+    hipStream_t manual_stream = nullptr;
+    Workspace manual_ws;
 
     void worker_loop(int slot);
+    bool take_batch(int slot, std::unique_lock<std::mutex> &lk, bool block, Batch &b,
+                    Workspace &ws);
+    void run_batch(int slot, const Batch &b, Workspace &ws, hipStream_t s);
     int pick_class(bool larger_ok) const;
     const Request *first_of(int cls) const;
     int64_t committed_except(int s) const;
@@ -173,6 +192,170 @@ void bt_engine::note_peaks() {
     peak_held = std::max(peak_held, h);
 }
 
+// Under mu: admits the next batch for `slot` into b.  With block, waits
+// until a batch can start (false only when the engine stops); without,
+// returns false when none can start now.
+bool bt_engine::take_batch(int slot, std::unique_lock<std::mutex> &lk, bool block, Batch &b,
+                           Workspace &ws) {
+    Slot &me = slots[(size_t)slot];
+    while (true) {
+        int cls = 0;
+        const auto ready = [&] {
+            if (stop) return true;
+            if (me.release) return true;
+            if (queue.empty()) return false;
+            int larger = 0;  // other slots running a batch of a larger class
+            for (size_t i = 0; i < slots.size(); ++i)
+                if ((int)i != slot && slots[i].busy && slots[i].cls > 0) ++larger;
+            cls = pick_class(slots.size() < 2 || larger < (int)slots.size() - 1);
+            if (cls < 0) return false;
+            const int64_t need = first_of(cls)->bytes;
+            const int64_t others = committed_except(slot);
+            if (others + need <= budget) return true;
+            // Idle slots whose cached workspaces stand in the way free them
+            // (woken only when a request to free is new, so idle slots do
+            // not wake each other in turn).
+            bool asked = false;
+            for (size_t i = 0; i < slots.size(); ++i)
+                if ((int)i != slot && !slots[i].busy && slots[i].held > 0 && !slots[i].release) {
+                    slots[i].release = true;
+                    asked = true;
+                }
+            if (asked) cv_work.notify_all();
+            return false;
+        };
+        if (block)
+            cv_work.wait(lk, ready);
+        else if (!ready())
+            return false;
+        if (stop) return false;  // destroy drains the queue before it stops workers
+        if (me.release) {  // idle and asked to free its cached workspace
+            me.release = false;
+            if (me.held > 0) {
+                lk.unlock();
+                ws.release();
+                lk.lock();
+                me.held = 0;
+                note_peaks();
+                cv_work.notify_all();
+            }
+            continue;
+        }
+        // If this slot's own cached workspace is what keeps the oldest
+        // request of the class out, free it first (its bytes stay counted
+        // until it is freed), then decide again.
+        const int64_t others = committed_except(slot);
+        if (me.held > 0 && others + me.held + first_of(cls)->bytes > budget) {
+            lk.unlock();
+            ws.release();
+            lk.lock();
+            me.held = 0;
+            note_peaks();
+            cv_work.notify_all();
+            continue;
+        }
+        // Admit requests of the chosen class in arrival order while the
+        // budget, this slot's cache included, allows.
+        const int32_t cap = cls == 2 ? std::min(max_batch, kLargePerBatch) : max_batch;
+        b = Batch{};
+        for (auto it = queue.begin(); it != queue.end() && (int32_t)b.reqs.size() < cap;) {
+            if (size_class_of(it->g.m) != cls) {
+                ++it;
+                continue;
+            }
+            if (others + me.held + b.bytes + it->bytes > budget) break;
+            b.bytes += it->bytes;
+            b.reqs.push_back(*it);
+            it = queue.erase(it);
+        }
+        b.held0 = me.held;
+        b.cls = cls;
+        me.res = b.bytes;
+        me.busy = true;
+        me.cls = cls;
+        running += (int64_t)b.reqs.size();
+        batches += 1;
+        admitted += (int64_t)b.reqs.size();
+        note_peaks();
+        if (verbose) {
+            int64_t edges = 0;
+            for (auto &r : b.reqs) edges += r.g.m;
+            std::fprintf(stderr, "[engine] %.1f ms slot %d admits %zu requests of class %d, %lld edges (queue %zu)\n",
+                         ms_since_created(), slot, b.reqs.size(), cls, (long long)edges,
+                         queue.size());
+        }
+        return true;
+    }
+}
+
+// Decomposes an admitted batch on the slot's stream and workspace (without
+// mu) and reports its requests as done.
+void bt_engine::run_batch(int slot, const Batch &b, Workspace &ws, hipStream_t s) {
+    std::vector<bt_csr> gs;
+    std::vector<int64_t *> sups, phis;
+    for (auto &r : b.reqs) {
+        gs.push_back(r.g);
+        sups.push_back(r.sup);
+        phis.push_back(r.phi);
+    }
+    // Once the index is built the peel's remaining need replaces what is
+    // left of the estimate, so other slots may admit against the
+    // difference.  The slot's commitment never grows past its admission
+    // (held0 + estimate); its real holdings are re-read at the end.
+    const SizedHook on_sized = [&](int64_t held, int64_t peel_bytes) {
+        std::lock_guard<std::mutex> lk(mu);
+        Slot &me = slots[(size_t)slot];
+        me.held = held;
+        me.res = std::max<int64_t>(0, std::min(peel_bytes, b.held0 + b.bytes - held));
+        note_peaks();
+        cv_work.notify_all();
+    };
+    std::vector<Done> out;
+    bt_stats bst{};
+    set_turn_weight(kClassTurnWeight[b.cls]);
+    try {
+        decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), &bst, ws,
+                             s, &on_sized);
+        for (auto &r : b.reqs) out.push_back(Done{r.id, BT_OK});
+    } catch (const Error &) {
+        // Isolate the failure: run the requests of the batch one by one.
+        for (auto &r : b.reqs) {
+            bt_status st = BT_OK;
+            try {
+                bt_csr g = r.g;
+                int64_t *sp = r.sup, *pp = r.phi;
+                decompose_batch_impl(&g, 1, &sp, &pp, nullptr, ws, s);
+            } catch (const Error &e) {
+                st = e.status;
+            } catch (...) {
+                st = BT_EDEVICE;
+            }
+            out.push_back(Done{r.id, st});
+        }
+    } catch (...) {
+        for (auto &r : b.reqs) out.push_back(Done{r.id, BT_EDEVICE});
+    }
+    set_turn_weight(-1);
+    const int64_t held_now = (int64_t)ws.bytes();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        Slot &me = slots[(size_t)slot];
+        me.held = held_now;
+        me.res = 0;
+        me.busy = false;
+        me.cls = -1;
+        note_peaks();
+        peel_yields += bst.peel_yields;
+        if (verbose)
+            std::fprintf(stderr, "[engine] %.1f ms slot %d done (%zu requests, %lld peel yields)\n",
+                         ms_since_created(), slot, b.reqs.size(), (long long)bst.peel_yields);
+        running -= (int64_t)b.reqs.size();
+        for (auto &d : out) done.push_back(d);
+    }
+    cv_work.notify_all();
+    cv_idle.notify_all();
+}
+
 void bt_engine::worker_loop(int slot) {
     (void)hipSetDevice(device);
     hipStream_t s = nullptr;
@@ -180,154 +363,12 @@ void bt_engine::worker_loop(int slot) {
     Workspace ws;  // cooperative peels of different slots take turns (see peel.hip)
     ws.bind_stream(s);
     while (true) {
-        std::vector<Request> batch;
-        int64_t bytes = 0, held0 = 0;
-        int batch_cls = 0;
+        Batch b;
         {
             std::unique_lock<std::mutex> lk(mu);
-            Slot &me = slots[(size_t)slot];
-            int cls = 0;
-            cv_work.wait(lk, [&] {
-                if (stop) return true;
-                if (me.release) return true;
-                if (queue.empty()) return false;
-                int larger = 0;  // other slots running a batch of a larger class
-                for (size_t i = 0; i < slots.size(); ++i)
-                    if ((int)i != slot && slots[i].busy && slots[i].cls > 0) ++larger;
-                cls = pick_class(slots.size() < 2 || larger < (int)slots.size() - 1);
-                if (cls < 0) return false;
-                const int64_t need = first_of(cls)->bytes;
-                const int64_t others = committed_except(slot);
-                if (others + need <= budget) return true;
-                // Idle slots whose cached workspaces stand in the way free them
-                // (woken only when a request to free is new, so idle slots do
-                // not wake each other in turn).
-                bool asked = false;
-                for (size_t i = 0; i < slots.size(); ++i)
-                    if ((int)i != slot && !slots[i].busy && slots[i].held > 0 &&
-                        !slots[i].release) {
-                        slots[i].release = true;
-                        asked = true;
-                    }
-                if (asked) cv_work.notify_all();
-                return false;
-            });
-            if (stop) break;  // destroy drains the queue before it stops workers
-            if (me.release) {  // idle and asked to free its cached workspace
-                me.release = false;
-                if (me.held > 0) {
-                    lk.unlock();
-                    ws.release();
-                    lk.lock();
-                    me.held = 0;
-                    note_peaks();
-                    cv_work.notify_all();
-                }
-                continue;
-            }
-            // If this slot's own cached workspace is what keeps the oldest
-            // request of the class out, free it first (its bytes stay
-            // counted until it is freed), then decide again.
-            const int64_t others = committed_except(slot);
-            if (me.held > 0 && others + me.held + first_of(cls)->bytes > budget) {
-                lk.unlock();
-                ws.release();
-                lk.lock();
-                me.held = 0;
-                note_peaks();
-                cv_work.notify_all();
-                continue;
-            }
-            // Admit requests of the chosen class in arrival order while the
-            // budget, this slot's cache included, allows.
-            const int32_t cap = cls == 2 ? std::min(max_batch, kLargePerBatch) : max_batch;
-            for (auto it = queue.begin(); it != queue.end() && (int32_t)batch.size() < cap;) {
-                if (size_class_of(it->g.m) != cls) {
-                    ++it;
-                    continue;
-                }
-                if (others + me.held + bytes + it->bytes > budget) break;
-                bytes += it->bytes;
-                batch.push_back(*it);
-                it = queue.erase(it);
-            }
-            held0 = me.held;
-            me.res = bytes;
-            me.busy = true;
-            me.cls = cls;
-            batch_cls = cls;
-            running += (int64_t)batch.size();
-            batches += 1;
-            admitted += (int64_t)batch.size();
-            note_peaks();
-            if (verbose) {
-                int64_t edges = 0;
-                for (auto &r : batch) edges += r.g.m;
-                std::fprintf(stderr, "[engine] %.1f ms slot %d admits %zu requests of class %d, %lld edges (queue %zu)\n",
-                             ms_since_created(), slot, batch.size(), cls, (long long)edges,
-                             queue.size());
-            }
+            if (!take_batch(slot, lk, true, b, ws)) break;
         }
-        std::vector<bt_csr> gs;
-        std::vector<int64_t *> sups, phis;
-        for (auto &r : batch) {
-            gs.push_back(r.g);
-            sups.push_back(r.sup);
-            phis.push_back(r.phi);
-        }
-        // Once the index is built the peel's remaining need replaces what is
-        // left of the estimate, so other slots may admit against the
-        // difference.  The slot's commitment never grows past its admission
-        // (held0 + estimate); its real holdings are re-read at the end.
-        const SizedHook on_sized = [&](int64_t held, int64_t peel_bytes) {
-            std::lock_guard<std::mutex> lk(mu);
-            Slot &me = slots[(size_t)slot];
-            me.held = held;
-            me.res = std::max<int64_t>(0, std::min(peel_bytes, held0 + bytes - held));
-            note_peaks();
-            cv_work.notify_all();
-        };
-        std::vector<Done> out;
-        bt_stats bst{};
-        set_turn_weight(kClassTurnWeight[batch_cls]);
-        try {
-            decompose_batch_impl(gs.data(), (int32_t)gs.size(), sups.data(), phis.data(), &bst,
-                                 ws, s, &on_sized);
-            for (auto &r : batch) out.push_back(Done{r.id, BT_OK});
-        } catch (const Error &) {
-            // Isolate the failure: run the requests of the batch one by one.
-            for (auto &r : batch) {
-                bt_status st = BT_OK;
-                try {
-                    decompose_batch_impl(&r.g, 1, &r.sup, &r.phi, nullptr, ws, s);
-                } catch (const Error &e) {
-                    st = e.status;
-                } catch (...) {
-                    st = BT_EDEVICE;
-                }
-                out.push_back(Done{r.id, st});
-            }
-        } catch (...) {
-            for (auto &r : batch) out.push_back(Done{r.id, BT_EDEVICE});
-        }
-        const int64_t held_now = (int64_t)ws.bytes();
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            Slot &me = slots[(size_t)slot];
-            me.held = held_now;
-            me.res = 0;
-            me.busy = false;
-            me.cls = -1;
-            note_peaks();
-            peel_yields += bst.peel_yields;
-            if (verbose)
-                std::fprintf(stderr, "[engine] %.1f ms slot %d done (%zu requests, %lld peel yields)\n",
-                             ms_since_created(), slot, batch.size(), (long long)bst.peel_yields);
-            running -= (int64_t)batch.size();
-            for (auto &d : out) done.push_back(d);
-        }
-        cv_work.notify_all();
-        cv_idle.notify_all();
+        run_batch(slot, b, ws, s);
     }
     ws.close();
     if (s) (void)hipStreamDestroy(s);
@@ -337,7 +378,7 @@ extern "C" {
 
 bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
                            bt_engine **out) {
-    if (!out || slots < 0 || max_batch < 0) {
+    if (!out || slots < -1 || max_batch < 0) {
         set_error("invalid engine arguments");
         return BT_EINVAL;
     }
@@ -355,9 +396,16 @@ bt_status bt_engine_create(int64_t hbm_budget, int32_t slots, int32_t max_batch,
         BT_HIP(hipStreamCreateWithFlags(&E->est_stream, hipStreamNonBlocking));
         E->est_ws.coop = false;
         E->est_ws.bind_stream(E->est_stream);
-        const int n = slots > 0 ? slots : kDefaultSlots;
-        E->slots.resize((size_t)n);
-        for (int i = 0; i < n; ++i) E->workers.emplace_back(&bt_engine::worker_loop, E, i);
+        if (slots == -1) {
+            E->manual = true;
+            BT_HIP(hipStreamCreateWithFlags(&E->manual_stream, hipStreamNonBlocking));
+            E->manual_ws.bind_stream(E->manual_stream);
+            E->slots.resize(1);
+        } else {
+            const int n = slots > 0 ? slots : kDefaultSlots;
+            E->slots.resize((size_t)n);
+            for (int i = 0; i < n; ++i) E->workers.emplace_back(&bt_engine::worker_loop, E, i);
+        }
     } catch (const Error &e) {
         set_error(e.msg);
         delete E;
@@ -418,10 +466,49 @@ bt_status bt_engine_poll(bt_engine *E, uint64_t *ids, int32_t *status, int32_t c
     return BT_OK;
 }
 
+bt_status bt_engine_step(bt_engine *E, int32_t *n_done) {
+    if (!E) {
+        set_error("engine is NULL");
+        return BT_EINVAL;
+    }
+    if (!E->manual) {
+        set_error("bt_engine_step needs an engine created with slots = -1 (this one runs "
+                  "its own worker threads)");
+        return BT_EINVAL;
+    }
+    std::lock_guard<std::mutex> step(E->step_mu);
+    Batch b;
+    {
+        std::unique_lock<std::mutex> lk(E->mu);
+        if (!E->take_batch(0, lk, false, b, E->manual_ws)) {
+            if (n_done) *n_done = 0;
+            return BT_OK;
+        }
+    }
+    (void)hipSetDevice(E->device);
+    E->run_batch(0, b, E->manual_ws, E->manual_stream);
+    if (n_done) *n_done = (int32_t)b.reqs.size();
+    return BT_OK;
+}
+
 bt_status bt_engine_drain(bt_engine *E) {
     if (!E) {
         set_error("engine is NULL");
         return BT_EINVAL;
+    }
+    if (E->manual) {
+        // Steps on the caller's thread until nothing is queued.
+        while (true) {
+            int32_t n = 0;
+            const bt_status st = bt_engine_step(E, &n);
+            if (st != BT_OK) return st;
+            if (n == 0) {
+                std::lock_guard<std::mutex> lk(E->mu);
+                if (E->queue.empty()) return BT_OK;
+                set_error("a queued request cannot be admitted");  // not reached: submit bounds them
+                return BT_EDEVICE;
+            }
+        }
     }
     std::unique_lock<std::mutex> lk(E->mu);
     E->cv_idle.wait(lk, [&] { return E->queue.empty() && E->running == 0; });
@@ -467,6 +554,8 @@ void bt_engine_destroy(bt_engine *E) {
     }
     E->cv_work.notify_all();
     for (auto &t : E->workers) t.join();
+    E->manual_ws.close();
+    if (E->manual_stream) (void)hipStreamDestroy(E->manual_stream);
     E->est_ws.close();
     if (E->est_stream) (void)hipStreamDestroy(E->est_stream);
     delete E;

@@ -40,10 +40,16 @@ def _csr(nu=3, nl=4, m=5, rp=0x1000, col=0x2000):
 def test_argument_errors_without_gpu():
     """Malformed descriptors and arguments are rejected before any device
     work, with the documented status and a message."""
-    L = binding.load()
+    L = binding._engine_lib()
     P = ctypes.c_void_p
     fake = P(0x3000)
+    handle = P(0)
+    n = ctypes.c_int32(0)
     cases = [
+        (lambda: L.bt_engine_create(0, -2, 0, ctypes.byref(handle)), binding.BT_EINVAL),
+        (lambda: L.bt_engine_create(0, 1, -1, ctypes.byref(handle)), binding.BT_EINVAL),
+        (lambda: L.bt_engine_step(None, ctypes.byref(n)), binding.BT_EINVAL),
+        (lambda: L.bt_engine_poll(None, None, None, 0, ctypes.byref(n)), binding.BT_EINVAL),
         (lambda: L.bt_decompose(None, None, fake, None, None), binding.BT_EINVAL),
         (lambda: L.bt_decompose(ctypes.byref(_csr(m=-1)), None, fake, None, None),
          binding.BT_EINVAL),

@@ -181,3 +181,49 @@ def test_engine_request_mix_alone_equals_mix():
     want = gold["big:1"]["per_graph"][0]["phi_sha256"]
     got = hashlib.sha256(eng.results[i0][2].cpu().numpy().astype("<i8").tobytes()).hexdigest()
     assert got == want
+
+
+def test_caller_driven_engine_steps():
+    """An engine created with slots = -1 has no worker threads: each
+    bt_engine_step admits one batch as a free slot would and decomposes it
+    on this thread; every result equals the plain decomposition; drain
+    steps until the queue is empty; a threaded engine refuses steps."""
+    gs = [synth.batch_graph(i) for i in range(24)] + [synth.scaled_chunglu(60_000, seed=16)]
+    dgs = [upload(g) for g in gs]
+    eng = binding.BtEngine(slots=-1)
+    try:
+        assert eng.bt_engine_step() == 0  # nothing queued
+        for i, d in enumerate(dgs):
+            eng.bt_engine_submit(d, i)
+        n1 = eng.bt_engine_step()
+        first = dict(eng.bt_engine_poll())
+        assert n1 > 0 and len(first) == n1
+        steps, total = 1, n1
+        while True:
+            k = eng.bt_engine_step()
+            if k == 0:
+                break
+            steps += 1
+            total += k
+        done = dict(first)
+        done.update(eng.bt_engine_poll())
+        assert total == len(gs) and sorted(done) == list(range(len(gs)))
+        assert all(st == binding.BT_OK for st in done.values())
+        st = eng.bt_engine_stats()
+        assert st["batches"] == steps >= 2 and st["queued"] == 0  # two size classes at least
+        for i, d in enumerate(dgs):
+            _, phi, _ = binding.bt_decompose(d, want_sup=False)
+            assert torch.equal(eng.results[i][2], phi), gs[i].name
+        for i, d in enumerate(dgs[:5]):
+            eng.bt_engine_submit(d, 100 + i)
+        eng.bt_engine_drain()
+        assert sorted(dict(eng.bt_engine_poll())) == [100, 101, 102, 103, 104]
+    finally:
+        eng.bt_engine_destroy()
+    threaded = binding.BtEngine(slots=1)
+    try:
+        with pytest.raises(binding.BtError) as ei:
+            threaded.bt_engine_step()
+        assert ei.value.status == binding.BT_EINVAL
+    finally:
+        threaded.bt_engine_destroy()
