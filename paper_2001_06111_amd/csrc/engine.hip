@@ -485,8 +485,13 @@ bt_status bt_engine_step(bt_engine *E, int32_t *n_done) {
             return BT_OK;
         }
     }
-    (void)hipSetDevice(E->device);
+    // The batch runs on the engine's device; the caller's current device is
+    // restored afterwards.
+    int prev = E->device;
+    (void)hipGetDevice(&prev);
+    if (prev != E->device) (void)hipSetDevice(E->device);
     E->run_batch(0, b, E->manual_ws, E->manual_stream);
+    if (prev != E->device) (void)hipSetDevice(prev);
     if (n_done) *n_done = (int32_t)b.reqs.size();
     return BT_OK;
 }
