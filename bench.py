@@ -410,8 +410,9 @@ def main():
     digest = sha_i64([p.cpu().numpy() for p in phis])
     want = golden.get(f"pool:{POOL}", {}).get("phi_sha256")
     check = "no-oracle-digest" if want is None else ("match" if want == digest else "MISMATCH")
+    # api.hip sets the union's edge order, which the traffic depends on.
     traffic = measured_traffic("peel_multi_pool4096_traffic.md",
-                               ("peel_multi.hip", "peel_common.h"))
+                               ("peel_multi.hip", "peel_common.h", "api.hip"))
     out = {
         "metric": "edges decomposed/s (bit-exact phi_e), batched vs plain; p50/p99 latency",
         "value": m_pool / (ms / 1000.0),
