@@ -475,7 +475,8 @@ def main():
         if key in args.single and key in inputs:
             if left(args.budget) > costs[key][1] + 10:
                 log(f"single {key}")
-                tr = measured_traffic("peel_chunglu5m_traffic.md", ("peel.hip", "peel_common.h")) \
+                tr = measured_traffic("peel_chunglu5m_traffic.md",
+                                      ("peel.hip", "peel_common.h", "api.hip")) \
                     if key == "c1" else None
                 singles[key] = single(key, inputs[key], 5 if key == "c1" else 20, 1, golden,
                                       traffic=tr)

@@ -160,12 +160,52 @@ void fill_stats(bt_stats *stats, const RankCSR &r, const IndexArrays &ix, const 
     stats->peel_yields = pc.yields;
 }
 
+const uint32_t *reorder_union(bt_csr &u, const int64_t *dvoff, int32_t ng, Workspace &ws,
+                              hipStream_t s);
+
+// Graphs from this many edges up are decomposed in the locality order (see
+// reorder_union); BT_REORDER=0 keeps the caller's numbering.
+constexpr int64_t kReorderMinEdges = int64_t(1) << 20;
+
+bool reorder_single(int64_t m) {
+    const char *v = std::getenv("BT_REORDER");
+    return m >= kReorderMinEdges && !(v && std::atoi(v) == 0);
+}
+
+// out[perm[p]] = t[p]: results back to the caller's edge order.
+__global__ void k_unpermute(const uint32_t *perm, int64_t m, const int64_t *sup_t,
+                            const int64_t *phi_t, int64_t *sup_out, int64_t *phi_out) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = perm[p];
+        if (sup_out) sup_out[e] = sup_t[p];
+        phi_out[e] = phi_t[p];
+    }
+}
+
 }  // namespace
 
-void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stats *stats,
+void decompose_impl(const bt_csr &g0, int64_t *sup_out0, int64_t *phi_out0, bt_stats *stats,
                     Workspace &ws, hipStream_t stream, bool unit_updates, bool auto_pc) {
     Events ev(stats != nullptr, stream);
     ev.mark(0);
+    // Large graphs peel in the locality order (each layer renumbered by
+    // decreasing degree, edges re-sorted), as batches do; the graph is
+    // validated first, since the reorder indexes by its ids.
+    bt_csr g = g0;
+    int64_t *sup_out = sup_out0, *phi_out = phi_out0;
+    const uint32_t *perm = nullptr;
+    if (phi_out0 && reorder_single(g0.m)) {
+        validate_graph(g0, ws, stream);
+        int64_t *dvoff = ws.get<int64_t>("reo_voff1", 4);
+        const int64_t hv[4] = {0, (int64_t)g0.n_lower, 0, (int64_t)g0.n_upper};
+        BT_HIP(hipMemcpyAsync(dvoff, hv, sizeof hv, hipMemcpyHostToDevice, stream));
+        perm = reorder_union(g, dvoff, 1, ws, stream);
+        if (perm) {
+            if (sup_out0) sup_out = ws.get<int64_t>("reo_sup", g0.m);
+            phi_out = ws.get<int64_t>("reo_phi", g0.m);
+        }
+    }
     RankCSR r;
     IndexArrays ix;
     build_all(g, r, ix, false, nullptr, ws, stream, &ev);
@@ -177,7 +217,7 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
         BT_HIP(hipMemcpyAsync(hb, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
         BT_HIP(hipStreamSynchronize(stream));
         if (hb[0] / g.m >= kAutoPcButterfliesPerEdge) {
-            decompose_pc_impl(g, kAutoPcTau, sup_out, phi_out, stats, ws, stream);
+            decompose_pc_impl(g0, kAutoPcTau, sup_out0, phi_out0, stats, ws, stream);
             return;
         }
     }
@@ -185,6 +225,11 @@ void decompose_impl(const bt_csr &g, int64_t *sup_out, int64_t *phi_out, bt_stat
     PeelOptions o;
     o.unit_updates = unit_updates;
     peel(r, ix, sup_out, phi_out, pc, ws, stream, &o);
+    if (perm) {
+        k_unpermute<<<grid_for(g0.m, 256, 16384), 256, 0, stream>>>(
+            perm, g0.m, sup_out0 ? sup_out : nullptr, phi_out, sup_out0, phi_out0);
+        BT_CHECK_LAUNCH();
+    }
     ev.mark(4);
     int64_t *hs = ws.host(2);
     BT_HIP(hipMemcpyAsync(hs, ix.butterflies, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
