@@ -512,7 +512,7 @@ def main():
         else:
             skipped["c2_pc"] = "budget"
         if args.c2_plain:
-            if left(args.budget) > 90:
+            if left(args.budget) > 60:
                 log("single c2 (plain peel)")
                 singles["c2_plain"] = single("c2", inputs["c2"], 1, 0, golden)
             else:
