@@ -359,7 +359,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--budget", type=float, default=540.0,
+    ap.add_argument("--budget", type=float, default=500.0,
                     help="wall seconds for the whole run; extras that would not fit are skipped")
     ap.add_argument("--single", default="c0,c1,c2",
                     help="single-graph lines: any of c0,c1,c2 (empty: none)")
