@@ -159,6 +159,9 @@ void bt_index_free(bt_index *idx);
  *   sup_out  device int64[m] (nullable): initial supports.
  *   phi_out  device int64[m]: bitruss numbers.
  *   stats    host (nullable): counters and per-phase device times.
+ * Graphs of 2^20 edges or more are peeled with each layer renumbered by
+ * decreasing degree (the support atomics then land close together); the
+ * outputs are always in the caller's edge order.
  */
 bt_status bt_decompose(const bt_csr *g, int64_t *sup_out, int64_t *phi_out,
                        bt_stats *stats, hipStream_t stream);
@@ -354,9 +357,10 @@ bt_status bt_decompose_batch(const bt_csr *gs, int32_t n_graphs, int64_t *const 
  *   estimate exceeds the whole budget.  Graph and outputs are caller-owned
  *   DEVICE memory that must stay valid until the request completes;
  *   sup_out may be NULL.  Results equal bt_decompose on the same graph.
- * A free slot admits, in arrival order, queued requests of the class of
- *   the oldest one that fit the budget left by the other slots, and
- *   decomposes them as one batch (bt_decompose_batch semantics).  A batch
+ * A free slot picks a size class (below) and admits, in arrival order,
+ *   queued requests of that class that fit the budget left by the other
+ *   slots, and decomposes them as one batch (bt_decompose_batch
+ *   semantics).  A batch
  *   holds one size class: below 2^14 edges, below 2^19, or larger (at most
  *   eight of those at a time).  The smallest class queued goes first, unless
  *   the oldest request of a larger class has waited 10 s.  Requests that
