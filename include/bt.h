@@ -320,8 +320,10 @@ bt_status bt_bitruss_components(const bt_csr *g, const int64_t *phi, int64_t k,
  * decomposed as disjoint unions of at most 2^26 edges (larger ones alone),
  * cut from the graphs in decreasing edge count; within a union every graph
  * peels at its own level when all of them have at most 2^19 edges, else
- * the union peels with one shared level.  Results equal bt_decompose on
- * each graph.
+ * the union peels with one shared level.  Inside a union each graph's
+ * vertices are renumbered by decreasing degree (the support atomics then
+ * land close together); results are written back in each caller's edge
+ * order and equal bt_decompose on each graph.
  * stats (nullable) receives the sums over all graphs; rounds and
  * peel_launches are summed over the unions, levels is the sum over the
  * unions of each union's largest per-graph level count.
